@@ -1,0 +1,290 @@
+/*
+ * fp8gemm.h - C ABI of the MI355X (gfx950) FP8 GEMM library, libfp8gemm.so.
+ *
+ * The operation (arXiv 2602.10262): FP8 x FP8 matrix products with FP32
+ * accumulation (Sec. 2, "FP8 Matrix Cores"), dense and with 2:4 structured
+ * sparsity along the reduction dimension (Sec. 2, "Structured Sparsity";
+ * Sec. 7), with the sparse encoding as a step of its own ahead of the product
+ * (Sec. 7.1.1, where the encoding cost is measured apart from the GEMM),
+ * independent GEMMs running concurrently on separate HIP streams (Sec. 6,
+ * Sec. 8.2), and transformer-style sequences of many GEMMs (Sec. 8.1).
+ *
+ * Conventions (every entry point):
+ *   - Plain C.  Every call returns fp8_status; fp8_last_error() returns a
+ *     thread-local text for the last failure of the calling thread.
+ *   - Tensor pointers are DEVICE pointers owned by the caller; the library
+ *     never frees them and keeps no reference after the call's stream work.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Kernel calls are asynchronous on it and never synchronise the host.
+ *   - FP8 formats are the OCP ones (E4M3: bias 7, max 448, no infinity;
+ *     E5M2: bias 15, max 57344, IEEE infinities).
+ *   - Shapes: M, N, K >= 1 (else FP8_ERR_SHAPE).  Leading dimensions are in
+ *     elements and at least the row length.  FP8 operand base pointers and
+ *     leading dimensions must be multiples of 16 bytes (else FP8_ERR_ALIGN).
+ *   - Argument checking is done on the host before any launch: a call that
+ *     returns an error has enqueued nothing.
+ */
+#ifndef FP8GEMM_H
+#define FP8GEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FP8_OK = 0,
+    FP8_ERR_ARG = 1,          /* null or inconsistent argument, workspace too small */
+    FP8_ERR_SHAPE = 2,        /* a dimension out of range */
+    FP8_ERR_ALIGN = 3,        /* pointer or leading dimension not 16-byte aligned */
+    FP8_ERR_UNSUPPORTED = 4,  /* valid request this build has no kernel for */
+    FP8_ERR_HIP = 5,          /* a HIP runtime call failed (text in fp8_last_error) */
+    FP8_ERR_NOMEM = 6,        /* a library-owned allocation failed */
+    FP8_ERR_BUDGET = 7,       /* server: request larger than the whole HBM budget */
+    FP8_ERR_CLOSED = 8,       /* server: shutting down */
+    FP8_ERR_PENDING = 9,      /* server: ticket not finished yet */
+    FP8_ERR_TIMEOUT = 10      /* server: wait timed out */
+} fp8_status;
+
+typedef enum { FP8_E4M3 = 0, FP8_E5M2 = 1 } fp8_fmt;
+typedef enum { FP8_OUT_F32 = 0, FP8_OUT_BF16 = 1 } fp8_out;
+/* TENSOR: one scale.  ROW: one per row of A (M values) / per column of B (N values). */
+typedef enum { FP8_SCALE_TENSOR = 0, FP8_SCALE_ROW = 1 } fp8_scale_kind;
+/* Which operand is 2:4-compressed.  A: the M x K activations; B: the weight,
+ * stored as its N x K transpose (one compressed row per output column). */
+typedef enum { FP8_SPARSE_A = 0, FP8_SPARSE_B = 1 } fp8_sparse_side;
+
+const char *fp8_last_error(void);
+int fp8_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Quantization: amax -> scale -> FP8 codes.                                 */
+/* ------------------------------------------------------------------------ */
+/* The per-tensor / per-row scaling that brings FP32 data into the FP8 range
+ * (the amax and scale reductions of the method).  For each tensor (kind =
+ * TENSOR) or each row (kind = ROW) of the row-major rows x cols FP32 matrix x:
+ *   amax = max |x|  (NaN if any element is NaN)
+ *   s = fl32(fmax / amax), d = fl32(1 / s)   (IEEE divisions; fmax = 448 for
+ *       E4M3, 57344 for E5M2); when amax is 0 or not finite, or s or d is 0
+ *       or not finite, s = d = 1
+ *   q = encode(fl32(x * s)): round to nearest even, saturating to +-fmax,
+ *       NaN -> 0x7F | sign, -0 kept.
+ * Outputs: q (row-major, ldq), scale = s and descale = d (1 or rows floats).
+ * ws: device workspace of fp8_quantize_workspace_size() bytes (4 bytes for
+ * TENSOR, 0 for ROW); its content need not be initialised.
+ * Requirements: x 16-byte aligned with ldx % 4 == 0, q aligned with
+ * ldq % 16 == 0. */
+fp8_status fp8_quantize_workspace_size(int64_t rows, int64_t cols, fp8_scale_kind kind, size_t *bytes);
+fp8_status fp8_quantize(const float *x, int64_t rows, int64_t cols, int64_t ldx, fp8_fmt fmt,
+                        fp8_scale_kind kind, uint8_t *q, int64_t ldq, float *scale, float *descale,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Dense GEMM.                                                               */
+/* ------------------------------------------------------------------------ */
+/* C = diag(d_a) * (dec(A) x dec(B)) * diag(d_b), accumulated in FP32 from
+ * exact FP8 products (Sec. 2: FP8 operands, FP32 accumulation), then
+ * C[i,j] = (acc[i,j] * d_a[i]) * d_b[j] in FP32, stored as FP32 or as BF16
+ * rounded to nearest even.
+ *   a: row-major M x K codes, leading dimension lda (bytes)
+ *   b: column-major K x N codes, i.e. N rows of K codes, leading dimension ldb
+ *   a_descale: 1 float (TENSOR) or M floats (ROW); b_descale: 1 or N floats
+ *   c: row-major M x N, leading dimension ldc (elements) */
+typedef struct {
+    int64_t M, N, K;
+    const uint8_t *a; fp8_fmt a_fmt; int64_t lda;
+    const uint8_t *b; fp8_fmt b_fmt; int64_t ldb;
+    const float *a_descale; fp8_scale_kind a_kind;
+    const float *b_descale; fp8_scale_kind b_kind;
+    void *c; fp8_out c_type; int64_t ldc;
+} fp8_gemm_args;
+
+/* Kernel choice: tile is an index into the table fp8_tile_info() describes
+ * (-1 = let the library choose: tuning cache, else heuristic); split_k >= 1
+ * splits the reduction into that many fixed-order partial sums (0 = choose). */
+typedef struct {
+    int tile;
+    int split_k;
+} fp8_plan;
+
+/* Describes compiled tile `tile`: macro-tile rows/cols and whether it is a
+ * sparse-capable kernel.  Returns FP8_ERR_ARG past the last tile. */
+fp8_status fp8_tile_info(int tile, int *block_m, int *block_n, int *waves, int *sparse);
+int fp8_num_tiles(void);
+
+/* The plan the library would use for these arguments (NULL plan = choose). */
+fp8_status fp8_gemm_plan_resolve(const fp8_gemm_args *args, const fp8_plan *plan, fp8_plan *resolved);
+fp8_status fp8_gemm_workspace_size(const fp8_gemm_args *args, const fp8_plan *plan, size_t *bytes);
+/* ws may be NULL when the workspace size is 0. */
+fp8_status fp8_gemm(const fp8_gemm_args *args, const fp8_plan *plan, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* 2:4 structured sparsity.                                                  */
+/* ------------------------------------------------------------------------ */
+/* Prunes a row-major rows x K code matrix to 2:4 along K (Sec. 2 and Sec. 7:
+ * two of every four consecutive elements become zero) and compresses it.
+ * In each group of four (k = 4g .. 4g+3) the two elements of largest
+ * magnitude survive, equal magnitudes going to the lower index; magnitude is
+ * compared on the 7-bit field code & 0x7F, which orders every finite code by
+ * |value| and ranks NaN/infinity codes above all finite ones.
+ *   values[r*ldv + 2g + t]: survivor t (t = 0, 1) in ascending index order
+ *   meta[r*ldm + g/2]: nibble g % 2 (low nibble = even g) = i0 | i1 << 2 with
+ *                      i0 < i1 the survivor positions; the little-endian
+ *                      32-bit word w of a row describes groups 8w .. 8w+7
+ *   mask[r*ldm + k/8]: bit k % 8 set iff element k survives (mask may be NULL)
+ * ldv = K/2 and ldm = K/8 (the compressed rows are packed).  K % 8 == 0 and
+ * the x/values/meta base pointers 16-byte aligned are required. */
+fp8_status fp8_sparse24_prune_compress(const uint8_t *x, fp8_fmt fmt, int64_t rows, int64_t K,
+                                       int64_t ldx, uint8_t *values, uint8_t *meta, uint8_t *mask,
+                                       void *stream);
+/* The pruned dense matrix: out[r*ldo + k] = survivor code or +0 (0x00). */
+fp8_status fp8_sparse24_decompress(const uint8_t *values, const uint8_t *meta, int64_t rows,
+                                   int64_t K, uint8_t *out, int64_t ldo, void *stream);
+
+/* C = A' x B with one operand given in the compressed form above.
+ *   side A: (values, meta) hold the compressed M x K activations; g.a unused.
+ *   side B: (values, meta) hold the compressed N x K transpose of B (a weight
+ *           in its natural N x K layout); g.b unused.
+ * Scales, formats and output as in fp8_gemm.  K % 128 == 0 is not required,
+ * K % 8 == 0 is.  The result equals fp8_gemm on the decompressed operand up
+ * to FP32 summation order. */
+typedef struct {
+    fp8_gemm_args g;
+    fp8_sparse_side side;
+    const uint8_t *values;
+    const uint8_t *meta;
+} fp8_sparse24_gemm_args;
+
+fp8_status fp8_sparse24_gemm_workspace_size(const fp8_sparse24_gemm_args *args, const fp8_plan *plan,
+                                            size_t *bytes);
+fp8_status fp8_sparse24_gemm(const fp8_sparse24_gemm_args *args, const fp8_plan *plan, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Autotuner.                                                                */
+/* ------------------------------------------------------------------------ */
+/* Times every (tile, split_k) candidate for these arguments on `stream` with
+ * HIP events (warmup, then iters timed launches, median taken), records the
+ * best in the in-process tuning cache and returns it.  The caller's c buffer
+ * is overwritten.  Workspace for the largest candidate is allocated by the
+ * library for the duration of the call.  Keyed on (M bucket, N, K, formats,
+ * output type, scale kinds, dense or sparse side). */
+fp8_status fp8_tune_gemm(const fp8_gemm_args *args, int iters, void *stream, fp8_plan *best,
+                         double *best_us);
+fp8_status fp8_tune_sparse24_gemm(const fp8_sparse24_gemm_args *args, int iters, void *stream,
+                                  fp8_plan *best, double *best_us);
+/* Persist / restore the tuning cache as JSON lines. */
+fp8_status fp8_tune_cache_save(const char *path);
+fp8_status fp8_tune_cache_load(const char *path);
+void fp8_tune_cache_clear(void);
+
+/* ------------------------------------------------------------------------ */
+/* Grouped GEMM: many independent problems in one persistent launch.         */
+/* ------------------------------------------------------------------------ */
+/* The batched form of the transformer-style sequence of FP8 GEMMs (Sec. 8.1):
+ * every problem is a dense or 2:4 GEMM as above (FP32 accumulation, split_k 1)
+ * and all of them run in one launch of a persistent kernel whose workgroups
+ * take output tiles from a device work list ordered longest-first.
+ * plan_create copies the problem descriptions to a device table (library
+ * owned); the problems' device buffers must stay valid while the plan is
+ * used.  tile: a tile index for every problem (-1 = library choice).
+ * fp8_grouped_gemm enqueues the work on `stream`; it allocates nothing and
+ * is capturable into a HIP graph.  With use_graph = 1 the first call captures
+ * the launch into a graph and later calls replay it (same stream required). */
+typedef struct {
+    int is_sparse;
+    fp8_gemm_args dense;            /* used when is_sparse == 0 */
+    fp8_sparse24_gemm_args sparse;  /* used when is_sparse == 1 */
+} fp8_group_problem;
+
+typedef struct fp8_grouped_plan fp8_grouped_plan;
+fp8_status fp8_grouped_plan_create(const fp8_group_problem *problems, int count, int tile,
+                                   int use_graph, fp8_grouped_plan **plan);
+fp8_status fp8_grouped_gemm(fp8_grouped_plan *plan, void *stream);
+fp8_status fp8_grouped_plan_info(const fp8_grouped_plan *plan, int *tile, int64_t *num_tiles,
+                                 int *num_workgroups);
+fp8_status fp8_grouped_plan_destroy(fp8_grouped_plan *plan);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a continuous-batching request loop over several HIP streams.     */
+/* ------------------------------------------------------------------------ */
+/* Independent GEMM requests issued concurrently on separate streams (the
+ * single-GPU analogue of the paper's concurrent-stream study, Sec. 6 and
+ * Sec. 8.2).  Each request multiplies FP32 activations x (M x K, device,
+ * quantized per token inside the server) by a registered FP8 weight (dense
+ * or 2:4-compressed N x K rows with per-channel descales) into c (M x N).
+ * A scheduler thread admits requests in arrival order while the transient
+ * device memory they need (quantized activations, scales, workspace) fits in
+ * hbm_budget_bytes and a stream slot is free, launches each on the least
+ * loaded of num_streams streams, and retires it when its completion event
+ * fires; requests that arrive meanwhile are admitted as memory and slots free
+ * up.  The result of a request does not depend on what else is in flight.
+ * Latency = completion - arrival, where arrival is the request's
+ * arrival_time_s on the server clock (seconds since fp8_server_create) or,
+ * when negative, the time of the submit call. */
+typedef struct {
+    size_t hbm_budget_bytes;
+    int num_streams;          /* 1 .. 16 */
+    int max_inflight;         /* 0 = 4 * num_streams */
+} fp8_server_config;
+
+typedef struct {
+    int64_t M;
+    int weight_id;
+    const float *x;           /* M x K FP32, row-major, ldx = K */
+    void *c;                  /* M x N, row-major, ldc = N */
+    fp8_out c_type;
+    fp8_fmt x_fmt;            /* FP8 format the activations are quantized to */
+    double arrival_time_s;
+} fp8_request;
+
+typedef struct {
+    double p50_ms, p99_ms, mean_ms, max_ms;
+    double tflops;            /* dense-equivalent 2*M*N*K over first arrival .. last completion */
+    double span_s;
+    double stream_cv;         /* coefficient of variation of per-stream busy time */
+    double fairness_range;    /* 1 - (t_max - t_min) / t_mean over per-stream busy time */
+    double fairness_minmax;   /* t_min / t_max over per-stream busy time */
+    uint64_t done, failed, rejected, peak_inflight;
+    size_t peak_bytes;
+} fp8_server_stats;
+
+typedef struct fp8_server fp8_server;
+fp8_status fp8_server_create(const fp8_server_config *cfg, fp8_server **srv);
+/* Registers a weight: dense (meta NULL: w is N x K codes) or 2:4 (w = values
+ * N x K/2, meta N x K/8).  w_descale: N floats.  Buffers stay caller-owned. */
+fp8_status fp8_server_register_weight(fp8_server *srv, const uint8_t *w, const uint8_t *meta,
+                                      const float *w_descale, int64_t N, int64_t K, fp8_fmt fmt,
+                                      int *weight_id);
+/* Thread-safe, non-blocking.  FP8_ERR_BUDGET if the request alone exceeds the budget. */
+fp8_status fp8_server_submit(fp8_server *srv, const fp8_request *req, uint64_t *ticket);
+fp8_status fp8_server_poll(fp8_server *srv, uint64_t ticket);                 /* OK or PENDING */
+fp8_status fp8_server_wait(fp8_server *srv, uint64_t ticket, int64_t timeout_us); /* <0: forever */
+/* Latency of a finished ticket in milliseconds. */
+fp8_status fp8_server_latency(fp8_server *srv, uint64_t ticket, double *ms);
+fp8_status fp8_server_drain(fp8_server *srv);
+fp8_status fp8_server_stats_get(fp8_server *srv, fp8_server_stats *stats);
+fp8_status fp8_server_reset_stats(fp8_server *srv);
+double fp8_server_now(fp8_server *srv);  /* seconds on the server clock */
+fp8_status fp8_server_destroy(fp8_server *srv);                               /* drains first */
+
+/* ------------------------------------------------------------------------ */
+/* Validator support: FP64 error norms on the device.                        */
+/* ------------------------------------------------------------------------ */
+/* Given the device result c (FP32 or BF16, M x N, ldc) and FP64 references
+ * cref, sabs (M x N, packed), accumulates over all elements:
+ *   out[0] = max |c - cref|, out[1] = max |c - cref| / bound,
+ *   out[2] = sum (c - cref)^2, out[3] = sum cref^2, out[4] = count over bound
+ * where bound = 4 K 2^-24 sabs (FP32) or (1 + 2^-8) 4 K 2^-24 sabs + 2^-8 |cref|
+ * (BF16).  out: 5 device doubles.  FP64 is used here only, never in a GEMM. */
+fp8_status fp8_validate(const void *c, fp8_out c_type, int64_t ldc, const double *cref,
+                        const double *sabs, int64_t M, int64_t N, int64_t K, double *out,
+                        void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FP8GEMM_H */

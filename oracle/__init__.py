@@ -54,6 +54,7 @@ def _load():
     lib.orc_encode_bitwise.restype = ctypes.c_uint8
     lib.orc_encode_sweep.argtypes = [I, ctypes.c_uint64, ctypes.c_uint64, I, ctypes.POINTER(ctypes.c_uint32)]
     lib.orc_encode_sweep.restype = ctypes.c_uint64
+    lib.orc_encode_range.argtypes = [I, ctypes.c_uint32, I64, P, I]
     lib.orc_scale.argtypes = [I, F, P, P]
     lib.orc_quantize.argtypes = [P, I64, I64, I64, I, I, P, I64, P, P]
     lib.orc_prune24.argtypes = [P, I, I64, I64, I64, P, P, P, P]
@@ -107,6 +108,14 @@ def encode_sweep(fmt: int, lo: int, hi: int, nthreads: int = 8):
     first = ctypes.c_uint32(0)
     bad = lib.orc_encode_sweep(fmt, lo, hi, nthreads, ctypes.byref(first))
     return int(bad), int(first.value)
+
+
+def encode_range(fmt: int, lo: int, n: int, nthreads: int | None = None) -> np.ndarray:
+    """Codes of the FP32 values whose bit patterns are lo, lo+1, ..., lo+n-1."""
+    lib = _load()
+    out = np.empty(n, np.uint8)
+    lib.orc_encode_range(fmt, lo, n, _ptr(out), nthreads or os.cpu_count() or 1)
+    return out
 
 
 def scale(fmt: int, amax: float):

@@ -435,3 +435,45 @@ void orc_gemm_at(const uint8_t *a, int a_fmt, int64_t lda, const uint8_t *b, int
     free(arow);
     free(j);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Batch encode of consecutive FP32 bit patterns (for exhaustive checks).      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int fmt;
+    uint32_t lo;
+    int64_t begin, end;
+    uint8_t *out;
+} range_job;
+
+static void *range_worker(void *p)
+{
+    range_job *j = (range_job *)p;
+    for (int64_t t = j->begin; t < j->end; ++t) {
+        uint32_t b = j->lo + (uint32_t)t;
+        float x;
+        memcpy(&x, &b, 4);
+        j->out[t] = orc_encode(j->fmt, x);
+    }
+    return NULL;
+}
+
+/* out[t] = orc_encode(fmt, the float whose bits are lo + t), t < n. */
+void orc_encode_range(int fmt, uint32_t lo, int64_t n, uint8_t *out, int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    range_job jobs[256];
+    int64_t step = (n + nthreads - 1) / nthreads;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].fmt = fmt;
+        jobs[t].lo = lo;
+        jobs[t].begin = step * t < n ? step * t : n;
+        jobs[t].end = step * (t + 1) < n ? step * (t + 1) : n;
+        jobs[t].out = out;
+        pthread_create(&th[t], NULL, range_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+}

@@ -1,1 +1,343 @@
-"""MI355X-native FP8 GEMM (dense and 2:4 structured-sparse) on gfx950."""
+"""MI355X-native FP8 GEMM (dense and 2:4 structured-sparse) for gfx950.
+
+Thin Python binding of libfp8gemm.so (include/fp8gemm.h): every function has
+the name of the C entry point it calls and only marshals arguments.  Device
+memory and streams come from PyTorch (tensors' data_ptr, the current stream);
+every step of the computation runs in the library's HIP kernels.  There is no
+fallback: if the library is not built, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfp8gemm.so")
+
+FP8_E4M3, FP8_E5M2 = 0, 1
+FP8_OUT_F32, FP8_OUT_BF16 = 0, 1
+FP8_SCALE_TENSOR, FP8_SCALE_ROW = 0, 1
+FP8_SPARSE_A, FP8_SPARSE_B = 0, 1
+STATUS = ["FP8_OK", "FP8_ERR_ARG", "FP8_ERR_SHAPE", "FP8_ERR_ALIGN", "FP8_ERR_UNSUPPORTED", "FP8_ERR_HIP",
+          "FP8_ERR_NOMEM", "FP8_ERR_BUDGET", "FP8_ERR_CLOSED", "FP8_ERR_PENDING", "FP8_ERR_TIMEOUT"]
+FP8_OK, FP8_ERR_PENDING, FP8_ERR_TIMEOUT = 0, 9, 10
+
+_P, _I64, _I, _SZ, _D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
+
+
+class GemmArgs(ctypes.Structure):
+    _fields_ = [("M", _I64), ("N", _I64), ("K", _I64),
+                ("a", _P), ("a_fmt", _I), ("lda", _I64),
+                ("b", _P), ("b_fmt", _I), ("ldb", _I64),
+                ("a_descale", _P), ("a_kind", _I),
+                ("b_descale", _P), ("b_kind", _I),
+                ("c", _P), ("c_type", _I), ("ldc", _I64)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("tile", _I), ("split_k", _I)]
+
+
+class Sparse24GemmArgs(ctypes.Structure):
+    _fields_ = [("g", GemmArgs), ("side", _I), ("values", _P), ("meta", _P)]
+
+
+class GroupProblem(ctypes.Structure):
+    _fields_ = [("is_sparse", _I), ("dense", GemmArgs), ("sparse", Sparse24GemmArgs)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", _SZ), ("num_streams", _I), ("max_inflight", _I)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("M", _I64), ("weight_id", _I), ("x", _P), ("c", _P), ("c_type", _I), ("x_fmt", _I),
+                ("arrival_time_s", _D)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("p50_ms", _D), ("p99_ms", _D), ("mean_ms", _D), ("max_ms", _D), ("tflops", _D),
+                ("span_s", _D), ("stream_cv", _D), ("fairness_range", _D), ("fairness_minmax", _D),
+                ("done", ctypes.c_uint64), ("failed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("peak_inflight", ctypes.c_uint64), ("peak_bytes", _SZ)]
+
+
+# Every exported entry point with its argument types (restype is fp8_status
+# unless listed in _RESTYPE).
+_SIGS = {
+    "fp8_last_error": [],
+    "fp8_version": [],
+    "fp8_quantize_workspace_size": [_I64, _I64, _I, _P],
+    "fp8_quantize": [_P, _I64, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _SZ, _P],
+    "fp8_tile_info": [_I, _P, _P, _P, _P],
+    "fp8_num_tiles": [],
+    "fp8_gemm_plan_resolve": [_P, _P, _P],
+    "fp8_gemm_workspace_size": [_P, _P, _P],
+    "fp8_gemm": [_P, _P, _P, _SZ, _P],
+    "fp8_sparse24_prune_compress": [_P, _I, _I64, _I64, _I64, _P, _P, _P, _P],
+    "fp8_sparse24_decompress": [_P, _P, _I64, _I64, _P, _I64, _P],
+    "fp8_sparse24_gemm_workspace_size": [_P, _P, _P],
+    "fp8_sparse24_gemm": [_P, _P, _P, _SZ, _P],
+    "fp8_tune_gemm": [_P, _I, _P, _P, _P],
+    "fp8_tune_sparse24_gemm": [_P, _I, _P, _P, _P],
+    "fp8_tune_cache_save": [ctypes.c_char_p],
+    "fp8_tune_cache_load": [ctypes.c_char_p],
+    "fp8_tune_cache_clear": [],
+    "fp8_grouped_plan_create": [_P, _I, _I, _I, _P],
+    "fp8_grouped_gemm": [_P, _P],
+    "fp8_grouped_plan_info": [_P, _P, _P, _P],
+    "fp8_grouped_plan_destroy": [_P],
+    "fp8_server_create": [_P, _P],
+    "fp8_server_register_weight": [_P, _P, _P, _P, _I64, _I64, _I, _P],
+    "fp8_server_submit": [_P, _P, _P],
+    "fp8_server_poll": [_P, ctypes.c_uint64],
+    "fp8_server_wait": [_P, ctypes.c_uint64, _I64],
+    "fp8_server_latency": [_P, ctypes.c_uint64, _P],
+    "fp8_server_drain": [_P],
+    "fp8_server_stats_get": [_P, _P],
+    "fp8_server_reset_stats": [_P],
+    "fp8_server_now": [_P],
+    "fp8_server_destroy": [_P],
+    "fp8_validate": [_P, _I, _I64, _P, _P, _I64, _I64, _I64, _P, _P],
+}
+_RESTYPE = {"fp8_last_error": ctypes.c_char_p, "fp8_version": _I, "fp8_num_tiles": _I,
+            "fp8_tune_cache_clear": None, "fp8_server_now": _D}
+
+_lib = None
+
+
+class Fp8Error(RuntimeError):
+    def __init__(self, fn: str, status: int, text: str):
+        name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"{fn}: {name}: {text}")
+        self.status = status
+
+
+def load() -> ctypes.CDLL:
+    """Loads libfp8gemm.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run paper_2602_10262_amd/build.py (or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        if not hasattr(lib, name):
+            continue
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = _RESTYPE.get(name, _I)
+    _lib = lib
+    return lib
+
+
+def _check(fn: str, status: int) -> int:
+    if status != FP8_OK:
+        raise Fp8Error(fn, status, load().fp8_last_error().decode())
+    return status
+
+
+def _call(fn: str, *args) -> int:
+    return _check(fn, getattr(load(), fn)(*args))
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream if hasattr(s, "cuda_stream") else int(s)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _u8(t):
+    import torch
+    return t.view(torch.uint8) if t.dtype != torch.uint8 else t
+
+
+# ---------------------------------------------------------------- quantize --
+
+def fp8_quantize(x, fmt: int = FP8_E4M3, kind: int = FP8_SCALE_TENSOR, q=None, scale=None, descale=None,
+                 ws=None, stream=None):
+    """FP32 rows x cols (CUDA tensor, row-major) -> (codes uint8, s, d)."""
+    import torch
+    rows, cols = x.shape
+    n = rows if kind == FP8_SCALE_ROW else 1
+    q = torch.empty((rows, (cols + 15) // 16 * 16), dtype=torch.uint8, device=x.device)[:, :cols] if q is None else q
+    scale = torch.empty(n, dtype=torch.float32, device=x.device) if scale is None else scale
+    descale = torch.empty(n, dtype=torch.float32, device=x.device) if descale is None else descale
+    if ws is None and kind == FP8_SCALE_TENSOR:
+        ws = torch.empty(16, dtype=torch.uint8, device=x.device)
+    _call("fp8_quantize", x.data_ptr(), rows, cols, x.stride(0), fmt, kind, q.data_ptr(), q.stride(0),
+          scale.data_ptr(), descale.data_ptr(), _ptr(ws), 0 if ws is None else ws.numel() * ws.element_size(),
+          _stream(stream))
+    return q, scale, descale
+
+
+# -------------------------------------------------------------------- gemm --
+
+def gemm_args(a, b_nk, a_descale, b_descale, c, a_fmt=FP8_E4M3, b_fmt=FP8_E4M3, c_type=None,
+              M=None, N=None, K=None) -> GemmArgs:
+    import torch
+    c_type = (FP8_OUT_BF16 if c.dtype == torch.bfloat16 else FP8_OUT_F32) if c_type is None else c_type
+    M = M if M is not None else (a.shape[0] if a is not None else c.shape[0])
+    N = N if N is not None else (b_nk.shape[0] if b_nk is not None else c.shape[1])
+    K = K if K is not None else (a.shape[1] if a is not None else b_nk.shape[1])
+    return GemmArgs(M, N, K,
+                    _ptr(a), a_fmt, a.stride(0) if a is not None else K,
+                    _ptr(b_nk), b_fmt, b_nk.stride(0) if b_nk is not None else K,
+                    a_descale.data_ptr(), FP8_SCALE_ROW if a_descale.numel() > 1 else FP8_SCALE_TENSOR,
+                    b_descale.data_ptr(), FP8_SCALE_ROW if b_descale.numel() > 1 else FP8_SCALE_TENSOR,
+                    c.data_ptr(), c_type, c.stride(0))
+
+
+def _plan(plan):
+    if plan is None:
+        return None
+    if isinstance(plan, Plan):
+        return ctypes.byref(plan)
+    tile, split = plan
+    return ctypes.byref(Plan(tile, split))
+
+
+def _workspace(size_fn, args_ref, plan_ref, device):
+    import torch
+    nbytes = ctypes.c_size_t(0)
+    _call(size_fn, args_ref, plan_ref, ctypes.byref(nbytes))
+    if nbytes.value == 0:
+        return None, 0
+    return torch.empty(nbytes.value, dtype=torch.uint8, device=device), nbytes.value
+
+
+def fp8_gemm(a, b_nk, a_descale, b_descale, a_fmt=FP8_E4M3, b_fmt=FP8_E4M3, out_dtype=None, c=None,
+             plan=None, ws=None, stream=None):
+    """C (M x N) = diag(d_a) dec(A) dec(B) diag(d_b); A: M x K codes, B given as N x K codes."""
+    import torch
+    if c is None:
+        c = torch.empty((a.shape[0], b_nk.shape[0]), dtype=out_dtype or torch.float32, device=a.device)
+    args = gemm_args(_u8(a), _u8(b_nk), a_descale, b_descale, c, a_fmt, b_fmt)
+    pref = _plan(plan)
+    if ws is None:
+        ws, nbytes = _workspace("fp8_gemm_workspace_size", ctypes.byref(args), pref, a.device)
+    else:
+        nbytes = ws.numel() * ws.element_size()
+    _call("fp8_gemm", ctypes.byref(args), pref, _ptr(ws), nbytes, _stream(stream))
+    return c
+
+
+def fp8_gemm_plan_resolve(args: GemmArgs, plan=None) -> tuple:
+    out = Plan(0, 0)
+    _call("fp8_gemm_plan_resolve", ctypes.byref(args), _plan(plan), ctypes.byref(out))
+    return out.tile, out.split_k
+
+
+def fp8_tile_info(tile: int) -> dict:
+    v = [ctypes.c_int(0) for _ in range(4)]
+    _call("fp8_tile_info", tile, *[ctypes.byref(x) for x in v])
+    return {"block_m": v[0].value, "block_n": v[1].value, "waves": v[2].value, "sparse": v[3].value}
+
+
+def fp8_num_tiles() -> int:
+    return load().fp8_num_tiles()
+
+
+# ------------------------------------------------------------------- 2:4 ----
+
+def fp8_sparse24_prune_compress(x, fmt=FP8_E4M3, with_mask=True, stream=None):
+    """Row-major rows x K codes -> (values rows x K/2, meta rows x K/8, mask rows x K/8 or None)."""
+    import torch
+    rows, K = x.shape
+    values = torch.empty((rows, K // 2), dtype=torch.uint8, device=x.device)
+    meta = torch.empty((rows, K // 8), dtype=torch.uint8, device=x.device)
+    mask = torch.empty((rows, K // 8), dtype=torch.uint8, device=x.device) if with_mask else None
+    _call("fp8_sparse24_prune_compress", _u8(x).data_ptr(), fmt, rows, K, x.stride(0), values.data_ptr(),
+          meta.data_ptr(), _ptr(mask), _stream(stream))
+    return values, meta, mask
+
+
+def fp8_sparse24_decompress(values, meta, K, out=None, stream=None):
+    import torch
+    rows = values.shape[0]
+    out = torch.empty((rows, K), dtype=torch.uint8, device=values.device) if out is None else out
+    _call("fp8_sparse24_decompress", values.data_ptr(), meta.data_ptr(), rows, K, out.data_ptr(), out.stride(0),
+          _stream(stream))
+    return out
+
+
+def sparse24_args(values, meta, dense, side, a_descale, b_descale, c, sparse_fmt=FP8_E4M3, dense_fmt=FP8_E4M3,
+                  M=None, N=None, K=None):
+    K = K if K is not None else values.shape[1] * 2
+    if side == FP8_SPARSE_A:
+        M = values.shape[0] if M is None else M
+        N = dense.shape[0] if N is None else N
+        g = gemm_args(None, _u8(dense), a_descale, b_descale, c, sparse_fmt, dense_fmt, M=M, N=N, K=K)
+    else:
+        M = dense.shape[0] if M is None else M
+        N = values.shape[0] if N is None else N
+        g = gemm_args(_u8(dense), None, a_descale, b_descale, c, dense_fmt, sparse_fmt, M=M, N=N, K=K)
+    return Sparse24GemmArgs(g, side, values.data_ptr(), meta.data_ptr())
+
+
+def fp8_sparse24_gemm(values, meta, dense, side, a_descale, b_descale, sparse_fmt=FP8_E4M3, dense_fmt=FP8_E4M3,
+                      out_dtype=None, c=None, plan=None, ws=None, stream=None):
+    """side A: C = A'(values, meta) x B, dense = B as N x K codes.
+    side B: C = A x B', dense = A (M x K codes), (values, meta) = compressed N x K weight."""
+    import torch
+    K = values.shape[1] * 2
+    M = values.shape[0] if side == FP8_SPARSE_A else dense.shape[0]
+    N = dense.shape[0] if side == FP8_SPARSE_A else values.shape[0]
+    if c is None:
+        c = torch.empty((M, N), dtype=out_dtype or torch.float32, device=values.device)
+    args = sparse24_args(values, meta, dense, side, a_descale, b_descale, c, sparse_fmt, dense_fmt, M, N, K)
+    pref = _plan(plan)
+    if ws is None:
+        ws, nbytes = _workspace("fp8_sparse24_gemm_workspace_size", ctypes.byref(args), pref, values.device)
+    else:
+        nbytes = ws.numel() * ws.element_size()
+    _call("fp8_sparse24_gemm", ctypes.byref(args), pref, _ptr(ws), nbytes, _stream(stream))
+    return c
+
+
+# ----------------------------------------------------------------- tuning ---
+
+def fp8_tune_gemm(args: GemmArgs, iters: int = 10, stream=None):
+    best = Plan(0, 0)
+    us = ctypes.c_double(0)
+    _call("fp8_tune_gemm", ctypes.byref(args), iters, _stream(stream), ctypes.byref(best), ctypes.byref(us))
+    return (best.tile, best.split_k), us.value
+
+
+def fp8_tune_sparse24_gemm(args: Sparse24GemmArgs, iters: int = 10, stream=None):
+    best = Plan(0, 0)
+    us = ctypes.c_double(0)
+    _call("fp8_tune_sparse24_gemm", ctypes.byref(args), iters, _stream(stream), ctypes.byref(best),
+          ctypes.byref(us))
+    return (best.tile, best.split_k), us.value
+
+
+def fp8_tune_cache_save(path: str):
+    _call("fp8_tune_cache_save", path.encode())
+
+
+def fp8_tune_cache_load(path: str):
+    _call("fp8_tune_cache_load", path.encode())
+
+
+def fp8_tune_cache_clear():
+    load().fp8_tune_cache_clear()
+
+
+# -------------------------------------------------------------- validate ----
+
+def fp8_validate(c, cref, sabs, K, stream=None) -> dict:
+    """FP64 error norms of c against FP64 references held on the device."""
+    import torch
+    M, N = c.shape
+    out = torch.empty(5, dtype=torch.float64, device=c.device)
+    c_type = FP8_OUT_BF16 if c.dtype == torch.bfloat16 else FP8_OUT_F32
+    _call("fp8_validate", c.data_ptr(), c_type, c.stride(0), cref.data_ptr(), sabs.data_ptr(), M, N, K,
+          out.data_ptr(), _stream(stream))
+    o = out.cpu().tolist()
+    return {"max_abs_err": o[0], "max_ratio": o[1], "normwise": (o[2] / o[3]) ** 0.5 if o[3] > 0 else o[2] ** 0.5,
+            "over": int(o[4]), "ok": o[4] == 0}

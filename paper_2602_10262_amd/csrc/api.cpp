@@ -1,0 +1,344 @@
+// C ABI of libfp8gemm.so: argument checks, plan choice and dispatch for
+// quantize, prune/compress, dense and 2:4 GEMM, validation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "api_util.hpp"
+
+namespace fp8k {
+
+static thread_local std::string g_err;
+
+fp8_status set_error(fp8_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+fp8_status hip_error(hipError_t e, const char *what)
+{
+    return set_error(FP8_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void clear_error() { g_err.clear(); }
+
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+static bool fmt_ok(int f) { return f == FP8_E4M3 || f == FP8_E5M2; }
+static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+static const int64_t kMaxDim = (int64_t)1 << 30;
+
+// Common checks of the dense description (the sparse side's operand is
+// checked by the caller instead).
+static fp8_status check_common(const fp8_gemm_args *a, bool need_a, bool need_b)
+{
+    if (!a) return set_error(FP8_ERR_ARG, "null args");
+    if (a->M < 1 || a->N < 1 || a->K < 1 || a->M > kMaxDim || a->N > kMaxDim || a->K > kMaxDim)
+        return set_error(FP8_ERR_SHAPE, "M, N, K must be in [1, 2^30]");
+    if ((int64_t)a->M * a->N > ((int64_t)1 << 40)) return set_error(FP8_ERR_SHAPE, "M*N too large");
+    if (!fmt_ok(a->a_fmt) || !fmt_ok(a->b_fmt)) return set_error(FP8_ERR_ARG, "unknown FP8 format");
+    if (a->c_type != FP8_OUT_F32 && a->c_type != FP8_OUT_BF16) return set_error(FP8_ERR_ARG, "unknown output type");
+    if ((a->a_kind != FP8_SCALE_TENSOR && a->a_kind != FP8_SCALE_ROW) ||
+        (a->b_kind != FP8_SCALE_TENSOR && a->b_kind != FP8_SCALE_ROW))
+        return set_error(FP8_ERR_ARG, "unknown scale kind");
+    if (!a->a_descale || !a->b_descale || !a->c) return set_error(FP8_ERR_ARG, "null descale or output pointer");
+    if (a->ldc < a->N) return set_error(FP8_ERR_ARG, "ldc < N");
+    if (need_a) {
+        if (!a->a) return set_error(FP8_ERR_ARG, "null A");
+        if (a->lda < a->K) return set_error(FP8_ERR_ARG, "lda < K");
+        if (!aligned16(a->a) || a->lda % 16) return set_error(FP8_ERR_ALIGN, "A pointer and lda must be 16-byte aligned");
+    }
+    if (need_b) {
+        if (!a->b) return set_error(FP8_ERR_ARG, "null B");
+        if (a->ldb < a->K) return set_error(FP8_ERR_ARG, "ldb < K");
+        if (!aligned16(a->b) || a->ldb % 16) return set_error(FP8_ERR_ALIGN, "B pointer and ldb must be 16-byte aligned");
+    }
+    return FP8_OK;
+}
+
+fp8_status prepare_dense(const fp8_gemm_args *a, Prepared &out)
+{
+    fp8_status st = check_common(a, true, true);
+    if (st != FP8_OK) return st;
+    GemmParams &p = out.p;
+    std::memset(&p, 0, sizeof(p));
+    p.a = a->a; p.lda = a->lda;
+    p.b = a->b; p.ldb = a->ldb;
+    p.si = a->a_descale; p.si_per = a->a_kind == FP8_SCALE_ROW;
+    p.sj = a->b_descale; p.sj_per = a->b_kind == FP8_SCALE_ROW;
+    p.c = a->c; p.ldc = a->ldc; p.out_bf16 = a->c_type == FP8_OUT_BF16; p.trans_out = 0;
+    p.M = (int)a->M; p.N = (int)a->N; p.K = (int)a->K;
+    p.splits = 1; p.kchunk = ((p.K + kBKHost - 1) / kBKHost) * kBKHost;
+    out.fa = a->a_fmt; out.fb = a->b_fmt; out.sparse = false;
+    out.key = GemmKey{a->M, a->N, a->K, out.fa, out.fb, p.out_bf16, p.si_per, p.sj_per, 0};
+    return FP8_OK;
+}
+
+fp8_status prepare_sparse(const fp8_sparse24_gemm_args *s, Prepared &out)
+{
+    if (!s) return set_error(FP8_ERR_ARG, "null args");
+    const fp8_gemm_args *a = &s->g;
+    const bool side_a = s->side == FP8_SPARSE_A;
+    if (s->side != FP8_SPARSE_A && s->side != FP8_SPARSE_B) return set_error(FP8_ERR_ARG, "unknown sparse side");
+    fp8_status st = check_common(a, !side_a, side_a);
+    if (st != FP8_OK) return st;
+    if (a->K % 8) return set_error(FP8_ERR_SHAPE, "2:4 GEMM needs K % 8 == 0");
+    if (!s->values || !s->meta) return set_error(FP8_ERR_ARG, "null compressed operand");
+    if (!aligned16(s->values) || !aligned16(s->meta))
+        return set_error(FP8_ERR_ALIGN, "compressed values and metadata must be 16-byte aligned");
+    GemmParams &p = out.p;
+    std::memset(&p, 0, sizeof(p));
+    p.a = s->values; p.lda = a->K / 2;
+    p.meta = s->meta; p.ldm = a->K / 8;
+    p.c = a->c; p.ldc = a->ldc; p.out_bf16 = a->c_type == FP8_OUT_BF16;
+    p.K = (int)a->K;
+    p.splits = 1; p.kchunk = ((p.K + kBKHost - 1) / kBKHost) * kBKHost;
+    if (side_a) {
+        p.b = a->b; p.ldb = a->ldb;
+        p.si = a->a_descale; p.si_per = a->a_kind == FP8_SCALE_ROW;
+        p.sj = a->b_descale; p.sj_per = a->b_kind == FP8_SCALE_ROW;
+        p.M = (int)a->M; p.N = (int)a->N; p.trans_out = 0;
+        out.fa = a->a_fmt; out.fb = a->b_fmt;
+    } else {
+        // C^T = W A^T: the compressed weight rows take the MFMA A slot.
+        p.b = a->a; p.ldb = a->lda;
+        p.si = a->b_descale; p.si_per = a->b_kind == FP8_SCALE_ROW;
+        p.sj = a->a_descale; p.sj_per = a->a_kind == FP8_SCALE_ROW;
+        p.M = (int)a->N; p.N = (int)a->M; p.trans_out = 1;
+        out.fa = a->b_fmt; out.fb = a->a_fmt;
+    }
+    out.sparse = true;
+    out.key = GemmKey{p.M, p.N, a->K, out.fa, out.fb, p.out_bf16, p.si_per, p.sj_per, side_a ? 1 : 2};
+    return FP8_OK;
+}
+
+void apply_split(GemmParams &p, int split_k)
+{
+    const int steps = (p.K + kBKHost - 1) / kBKHost;
+    int s = std::max(1, std::min(split_k, steps));
+    const int per = (steps + s - 1) / s;
+    s = (steps + per - 1) / per;   // no empty split
+    p.splits = s;
+    p.kchunk = per * kBKHost;
+}
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Split count that brings a grid of nb tiles to about two workgroups per CU
+// while keeping at least four K steps per split.
+static int default_splits(int64_t nb, int64_t K)
+{
+    const int64_t steps = cdiv(K, kBKHost);
+    int64_t want = 1;
+    if (nb < 256) want = std::min<int64_t>(cdiv(512, nb), std::max<int64_t>(1, steps / 4));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, 64));
+}
+
+fp8_plan heuristic_plan(const GemmKey &k)
+{
+    fp8_plan p;
+    const int64_t M = k.mk, N = k.nk;
+    if (N <= 16) p.tile = 8;
+    else if (N <= 32) p.tile = 9;
+    else if (M <= 16) p.tile = 4;
+    else if (M <= 32) p.tile = 5;
+    else if (M <= 64) p.tile = 7;
+    else if (M <= 128 || N <= 128) p.tile = 0;
+    else p.tile = 1;
+    const TileDesc &t = tile_desc(p.tile);
+    p.split_k = default_splits(cdiv(M, t.bm) * cdiv(N, t.bn), k.kk);
+    return p;
+}
+
+fp8_status resolve_plan(const Prepared &pr, const fp8_plan *plan, fp8_plan &res)
+{
+    if (!tune_cache_lookup(pr.key, res)) res = heuristic_plan(pr.key);
+    if (plan) {
+        if (plan->tile >= num_tiles()) return set_error(FP8_ERR_ARG, "plan.tile out of range");
+        if (plan->tile >= 0) {
+            res.tile = plan->tile;
+            const TileDesc &t = tile_desc(res.tile);
+            res.split_k = default_splits(cdiv(pr.key.mk, t.bm) * cdiv(pr.key.nk, t.bn), pr.key.kk);
+        }
+        if (plan->split_k > 0) res.split_k = plan->split_k;
+    }
+    if (res.split_k < 1) res.split_k = 1;
+    GemmParams p = pr.p;
+    apply_split(p, res.split_k);
+    res.split_k = p.splits;
+    return FP8_OK;
+}
+
+size_t workspace_bytes(const Prepared &pr, const fp8_plan &res)
+{
+    GemmParams p = pr.p;
+    apply_split(p, res.split_k);
+    if (p.splits <= 1) return 0;
+    return (size_t)p.splits * (size_t)p.M * (size_t)p.N * sizeof(float);
+}
+
+fp8_status run_prepared(Prepared pr, const fp8_plan &res, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    apply_split(pr.p, res.split_k);
+    const size_t need = workspace_bytes(pr, res);
+    if (need > 0) {
+        if (!ws || ws_bytes < need) return set_error(FP8_ERR_ARG, "workspace too small: need " + std::to_string(need));
+        pr.p.ws = static_cast<float *>(ws);
+    }
+    hipError_t e = launch_gemm(res.tile, pr.fa, pr.fb, pr.sparse, pr.p, st);
+    if (e != hipSuccess) return hip_error(e, "gemm launch");
+    if (pr.p.splits > 1) {
+        e = launch_splitk_reduce(pr.p, st);
+        if (e != hipSuccess) return hip_error(e, "split-K reduce launch");
+    }
+    return FP8_OK;
+}
+
+}  // namespace fp8k
+
+using namespace fp8k;
+
+extern "C" {
+
+const char *fp8_last_error(void) { return g_err.c_str(); }
+int fp8_version(void) { return 1; }
+
+fp8_status fp8_quantize_workspace_size(int64_t rows, int64_t cols, fp8_scale_kind kind, size_t *bytes)
+{
+    if (!bytes) return set_error(FP8_ERR_ARG, "null bytes");
+    if (rows < 1 || cols < 1) return set_error(FP8_ERR_SHAPE, "rows, cols must be >= 1");
+    *bytes = kind == FP8_SCALE_TENSOR ? 4 : 0;
+    return FP8_OK;
+}
+
+fp8_status fp8_quantize(const float *x, int64_t rows, int64_t cols, int64_t ldx, fp8_fmt fmt, fp8_scale_kind kind,
+                        uint8_t *q, int64_t ldq, float *scale, float *descale, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    if (!x || !q || !scale || !descale) return set_error(FP8_ERR_ARG, "null pointer");
+    if (rows < 1 || cols < 1 || rows > kMaxDim || cols > kMaxDim) return set_error(FP8_ERR_SHAPE, "rows, cols out of range");
+    if (!fmt_ok(fmt)) return set_error(FP8_ERR_ARG, "unknown FP8 format");
+    if (kind != FP8_SCALE_TENSOR && kind != FP8_SCALE_ROW) return set_error(FP8_ERR_ARG, "unknown scale kind");
+    if (ldx < cols || ldq < cols) return set_error(FP8_ERR_ARG, "leading dimension < cols");
+    if (!aligned16(x) || ldx % 4) return set_error(FP8_ERR_ALIGN, "x must be 16-byte aligned with ldx % 4 == 0");
+    if (!aligned16(q) || ldq % 16) return set_error(FP8_ERR_ALIGN, "q must be 16-byte aligned with ldq % 16 == 0");
+    if (kind == FP8_SCALE_TENSOR && (!ws || ws_bytes < 4)) return set_error(FP8_ERR_ARG, "workspace too small: need 4");
+    hipError_t e = launch_quantize(x, rows, cols, ldx, fmt, kind == FP8_SCALE_ROW, q, ldq, scale, descale, ws,
+                                   as_stream(stream));
+    if (e != hipSuccess) return hip_error(e, "quantize launch");
+    return FP8_OK;
+}
+
+fp8_status fp8_tile_info(int tile, int *block_m, int *block_n, int *waves, int *sparse)
+{
+    if (tile < 0 || tile >= num_tiles()) return set_error(FP8_ERR_ARG, "tile out of range");
+    const TileDesc &t = tile_desc(tile);
+    if (block_m) *block_m = t.bm;
+    if (block_n) *block_n = t.bn;
+    if (waves) *waves = t.waves;
+    if (sparse) *sparse = t.sparse_ok;
+    return FP8_OK;
+}
+
+int fp8_num_tiles(void) { return num_tiles(); }
+
+fp8_status fp8_gemm_plan_resolve(const fp8_gemm_args *args, const fp8_plan *plan, fp8_plan *resolved)
+{
+    if (!resolved) return set_error(FP8_ERR_ARG, "null resolved");
+    Prepared pr;
+    fp8_status st = prepare_dense(args, pr);
+    if (st != FP8_OK) return st;
+    return resolve_plan(pr, plan, *resolved);
+}
+
+fp8_status fp8_gemm_workspace_size(const fp8_gemm_args *args, const fp8_plan *plan, size_t *bytes)
+{
+    if (!bytes) return set_error(FP8_ERR_ARG, "null bytes");
+    Prepared pr;
+    fp8_status st = prepare_dense(args, pr);
+    if (st != FP8_OK) return st;
+    fp8_plan res;
+    st = resolve_plan(pr, plan, res);
+    if (st != FP8_OK) return st;
+    *bytes = workspace_bytes(pr, res);
+    return FP8_OK;
+}
+
+fp8_status fp8_gemm(const fp8_gemm_args *args, const fp8_plan *plan, void *ws, size_t ws_bytes, void *stream)
+{
+    Prepared pr;
+    fp8_status st = prepare_dense(args, pr);
+    if (st != FP8_OK) return st;
+    fp8_plan res;
+    st = resolve_plan(pr, plan, res);
+    if (st != FP8_OK) return st;
+    return run_prepared(pr, res, ws, ws_bytes, as_stream(stream));
+}
+
+fp8_status fp8_sparse24_prune_compress(const uint8_t *x, fp8_fmt fmt, int64_t rows, int64_t K, int64_t ldx,
+                                       uint8_t *values, uint8_t *meta, uint8_t *mask, void *stream)
+{
+    if (!x || !values || !meta) return set_error(FP8_ERR_ARG, "null pointer");
+    if (!fmt_ok(fmt)) return set_error(FP8_ERR_ARG, "unknown FP8 format");
+    if (rows < 1 || K < 1 || rows > kMaxDim || K > kMaxDim) return set_error(FP8_ERR_SHAPE, "rows, K out of range");
+    if (K % 8) return set_error(FP8_ERR_SHAPE, "K % 8 != 0");
+    if (ldx < K) return set_error(FP8_ERR_ARG, "ldx < K");
+    if (!aligned16(x) || ldx % 16 || !aligned16(values) || !aligned16(meta) || (mask && !aligned16(mask)))
+        return set_error(FP8_ERR_ALIGN, "pointers and ldx must be 16-byte aligned");
+    hipError_t e = launch_prune24(x, rows, K, ldx, values, meta, mask, as_stream(stream));
+    if (e != hipSuccess) return hip_error(e, "prune launch");
+    return FP8_OK;
+}
+
+fp8_status fp8_sparse24_decompress(const uint8_t *values, const uint8_t *meta, int64_t rows, int64_t K, uint8_t *out,
+                                   int64_t ldo, void *stream)
+{
+    if (!values || !meta || !out) return set_error(FP8_ERR_ARG, "null pointer");
+    if (rows < 1 || K < 1 || rows > kMaxDim || K > kMaxDim) return set_error(FP8_ERR_SHAPE, "rows, K out of range");
+    if (K % 8) return set_error(FP8_ERR_SHAPE, "K % 8 != 0");
+    if (ldo < K) return set_error(FP8_ERR_ARG, "ldo < K");
+    hipError_t e = launch_decompress24(values, meta, rows, K, out, ldo, as_stream(stream));
+    if (e != hipSuccess) return hip_error(e, "decompress launch");
+    return FP8_OK;
+}
+
+fp8_status fp8_sparse24_gemm_workspace_size(const fp8_sparse24_gemm_args *args, const fp8_plan *plan, size_t *bytes)
+{
+    if (!bytes) return set_error(FP8_ERR_ARG, "null bytes");
+    Prepared pr;
+    fp8_status st = prepare_sparse(args, pr);
+    if (st != FP8_OK) return st;
+    fp8_plan res;
+    st = resolve_plan(pr, plan, res);
+    if (st != FP8_OK) return st;
+    *bytes = workspace_bytes(pr, res);
+    return FP8_OK;
+}
+
+fp8_status fp8_sparse24_gemm(const fp8_sparse24_gemm_args *args, const fp8_plan *plan, void *ws, size_t ws_bytes,
+                             void *stream)
+{
+    Prepared pr;
+    fp8_status st = prepare_sparse(args, pr);
+    if (st != FP8_OK) return st;
+    fp8_plan res;
+    st = resolve_plan(pr, plan, res);
+    if (st != FP8_OK) return st;
+    return run_prepared(pr, res, ws, ws_bytes, as_stream(stream));
+}
+
+fp8_status fp8_validate(const void *c, fp8_out c_type, int64_t ldc, const double *cref, const double *sabs, int64_t M,
+                        int64_t N, int64_t K, double *out, void *stream)
+{
+    if (!c || !cref || !sabs || !out) return set_error(FP8_ERR_ARG, "null pointer");
+    if (M < 1 || N < 1 || K < 1) return set_error(FP8_ERR_SHAPE, "M, N, K must be >= 1");
+    if (ldc < N) return set_error(FP8_ERR_ARG, "ldc < N");
+    hipError_t e = launch_validate(c, c_type == FP8_OUT_BF16, ldc, cref, sabs, M, N, K, out, as_stream(stream));
+    if (e != hipSuccess) return hip_error(e, "validate launch");
+    return FP8_OK;
+}
+
+}  // extern "C"

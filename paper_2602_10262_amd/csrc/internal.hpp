@@ -1,0 +1,65 @@
+// Host-side declarations shared by the kernel files and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fp8k {
+
+constexpr int kBKHost = 128;   // K step of every GEMM kernel (codes)
+
+// One GEMM as the kernels see it.  The "i" operand sits in the MFMA A slot
+// (dense rows, or 2:4-compressed values + metadata when sparse), the "j"
+// operand in the MFMA B slot (always dense rows of K codes).  The result
+// element (i, j) is stored at c[i*ldc + j], or at c[j*ldc + i] when
+// trans_out is set (used when the compressed operand is the weight).
+struct GemmParams {
+    const uint8_t *a;      // i operand: dense M x K (lda) or compressed values M x K/2 (lda)
+    const uint8_t *meta;   // i operand metadata M x K/8 (ldm) when sparse
+    const uint8_t *b;      // j operand: N x K (ldb)
+    const float *si;       // descale of row i (or one for all rows)
+    const float *sj;       // descale of column j (or one)
+    void *c;
+    float *ws;             // split-K partial sums [splits][M][N] when splits > 1
+    int64_t lda, ldm, ldb, ldc;
+    int M, N, K;
+    int si_per, sj_per;    // 1: one descale per row / column
+    int out_bf16;
+    int trans_out;         // store transposed; descales then apply j first
+    int splits;            // >= 1
+    int kchunk;            // K range per split, a multiple of 128
+};
+
+struct TileDesc {
+    int bm, bn, waves, sparse_ok;
+};
+
+int num_tiles();
+const TileDesc &tile_desc(int t);
+
+hipError_t launch_gemm(int tile, int fa, int fb, bool sparse, const GemmParams &p, hipStream_t st);
+hipError_t launch_splitk_reduce(const GemmParams &p, hipStream_t st);
+
+hipError_t launch_quantize(const float *x, int64_t rows, int64_t cols, int64_t ldx, int fmt, int per_row,
+                           uint8_t *q, int64_t ldq, float *s, float *d, void *ws, hipStream_t st);
+hipError_t launch_encode_bits(int fmt, uint32_t lo, int64_t n, uint8_t *out, hipStream_t st);
+
+hipError_t launch_prune24(const uint8_t *x, int64_t rows, int64_t K, int64_t ldx, uint8_t *values,
+                          uint8_t *meta, uint8_t *mask, hipStream_t st);
+hipError_t launch_decompress24(const uint8_t *values, const uint8_t *meta, int64_t rows, int64_t K,
+                               uint8_t *out, int64_t ldo, hipStream_t st);
+
+hipError_t launch_validate(const void *c, int out_bf16, int64_t ldc, const double *cref, const double *sabs,
+                           int64_t M, int64_t N, int64_t K, double *out, hipStream_t st);
+
+// Grouped persistent GEMM.
+struct GroupEntry {
+    GemmParams p;          // splits == 1
+    int sparse;
+    int tiles_m, tiles_n;
+    int64_t tile_begin;    // prefix sum of tiles over the work list
+};
+hipError_t launch_grouped(int tile, int fa, int fb, const GroupEntry *table, int count, int64_t total_tiles,
+                          int *counter, int grid, hipStream_t st);
+int grouped_max_workgroups(int tile);
+
+}  // namespace fp8k
