@@ -29,41 +29,46 @@ __device__ __forceinline__ void tile_coords(int M, int N, int &tm, int &tn)
     tn = in / rows_in_group;
 }
 
-template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP>
-__global__ void __launch_bounds__(WM *WN * 64) gemm_kernel(GemmParams p)
+template <int BM, int BN, int WM, int WN, int OCC, int PF, int FA, int FB, bool SP, bool KFAST>
+__global__ void __launch_bounds__(WM *WN * 64, OCC) gemm_kernel(GemmParams p)
 {
     __shared__ __attribute__((aligned(16))) uint8_t smem[TileSmem<BM, BN, SP>::TOTAL];
     int tm, tn;
     tile_coords<BM, BN>(p.M, p.N, tm, tn);
-    gemm_tile<BM, BN, WM, WN, FA, FB, SP>(p, tm, tn, blockIdx.z, smem);
+    gemm_tile<BM, BN, WM, WN, FA, FB, SP, KFAST, PF>(p, tm, tn, blockIdx.z, smem);
 }
 
-// Tile table: (BM, BN, WM, WN).  Index = plan.tile.
-#define FP8_TILE_LIST(X)      \
-    X(0, 128, 128, 2, 2)      \
-    X(1, 256, 128, 2, 2)      \
-    X(2, 256, 256, 2, 2)      \
-    X(3, 64, 64, 1, 1)        \
-    X(4, 16, 64, 1, 1)        \
-    X(5, 32, 128, 1, 2)       \
-    X(6, 128, 256, 2, 2)      \
-    X(7, 64, 256, 1, 4)       \
-    X(8, 128, 16, 4, 1)       \
-    X(9, 256, 32, 4, 1)
+// Tile table: (BM, BN, WM, WN, workgroups per CU the registers are sized
+// for, prefetch depth in K steps).  Index = plan.tile.
+#define FP8_TILE_LIST(X)           \
+    X(0, 128, 128, 2, 2, 2, 2)     \
+    X(1, 256, 128, 2, 2, 1, 1)     \
+    X(2, 256, 256, 2, 2, 1, 1)     \
+    X(3, 64, 64, 1, 1, 8, 2)       \
+    X(4, 16, 64, 1, 1, 8, 2)       \
+    X(5, 32, 128, 1, 2, 4, 2)      \
+    X(6, 128, 256, 2, 2, 1, 1)     \
+    X(7, 64, 256, 1, 4, 2, 2)      \
+    X(8, 128, 16, 4, 1, 2, 2)      \
+    X(9, 256, 32, 4, 1, 2, 2)      \
+    X(10, 256, 256, 2, 4, 1, 1)    \
+    X(11, 256, 256, 4, 2, 1, 1)    \
+    X(12, 256, 128, 4, 2, 1, 2)    \
+    X(13, 128, 256, 2, 4, 1, 2)
 
-#define FP8_DESC(i, bm, bn, wm, wn) {bm, bn, wm * wn, 1},
+#define FP8_DESC(i, bm, bn, wm, wn, occ, pf) {bm, bn, wm * wn, 1},
 static const TileDesc kTiles[] = {FP8_TILE_LIST(FP8_DESC)};
 #undef FP8_DESC
 
 int num_tiles() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
 const TileDesc &tile_desc(int t) { return kTiles[t]; }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int OCC, int PF, bool KFAST = true>
 static hipError_t launch_one(int fa, int fb, bool sp, const GemmParams &p, hipStream_t st)
 {
     const int nb = ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN);
     dim3 grid((unsigned)nb, 1, (unsigned)p.splits), block(WM * WN * 64);
-#define FP8_GO(FA, FB, SP) gemm_kernel<BM, BN, WM, WN, FA, FB, SP><<<grid, block, 0, st>>>(p)
+#define FP8_GO(FA, FB, SP) gemm_kernel<BM, BN, WM, WN, OCC, PF, FA, FB, SP, KFAST><<<grid, block, 0, st>>>(p)
     const int key = fa * 4 + fb * 2 + (sp ? 1 : 0);
     switch (key) {
     case 0: FP8_GO(0, 0, false); break;
@@ -79,11 +84,16 @@ static hipError_t launch_one(int fa, int fb, bool sp, const GemmParams &p, hipSt
     return hipGetLastError();
 }
 
+bool k_is_fast(bool sparse, int K) { return sparse ? (K % 128) == 0 : (K % 16) == 0; }
+
 hipError_t launch_gemm(int tile, int fa, int fb, bool sparse, const GemmParams &p, hipStream_t st)
 {
+    // A K that leaves partial 16-byte chunks runs on the byte-exact loader,
+    // compiled for the 128 x 128 tile only.
+    if (!k_is_fast(sparse, p.K)) return launch_one<128, 128, 2, 2, 1, 1, false>(fa, fb, sparse, p, st);
     switch (tile) {
-#define FP8_CASE(i, bm, bn, wm, wn) \
-    case i: return launch_one<bm, bn, wm, wn>(fa, fb, sparse, p, st);
+#define FP8_CASE(i, bm, bn, wm, wn, occ, pf) \
+    case i: return launch_one<bm, bn, wm, wn, occ, pf>(fa, fb, sparse, p, st);
         FP8_TILE_LIST(FP8_CASE)
 #undef FP8_CASE
     default: return hipErrorInvalidValue;

@@ -2,13 +2,14 @@
 //
 // One workgroup computes a BM x BN block of C over a K range, in steps of 128
 // codes of K:
-//   - stage loads: 128-bit global loads of the next step's A and B tiles are
-//     issued into registers before the current step's MFMAs and written to
-//     the other half of a double-buffered LDS area after them, so one
-//     barrier per step suffices;
+//   - stage loads: 128-bit global loads of step k+2 are issued into one of
+//     two register sets before the MFMAs of step k, and the other set (step
+//     k+1, loaded during step k-1) is written to the other half of a
+//     double-buffered LDS area after them: two steps of compute cover the
+//     global latency and one barrier per step suffices;
 //   - LDS layout: dense operands keep one 128-byte row per tile row, the
-//     sixteen-byte chunks of row r permuted by XOR with (r >> 1) & 7 so that
-//     the sixteen rows a fragment read touches spread over all banks;
+//     sixteen-byte chunks of row r permuted by an XOR with the row number
+//     so that the sixteen rows a fragment read touches spread over all banks;
 //     compressed operands keep 64 value bytes and 16 metadata bytes per row;
 //   - each wave owns a (BM / WM) x (BN / WN) sub-block made of 16 x 16
 //     accumulators; per step it reads its A and B fragments from LDS and
@@ -37,11 +38,16 @@ struct TileSmem {
     static constexpr int TOTAL = 2 * STAGE;
 };
 
-__device__ __forceinline__ int swz(int r, int c) { return (r * 128) + ((c ^ ((r >> 1) & 7)) << 4); }
+// Chunk c of tile row r sits at chunk c ^ g(r), g(r) = (r & 7) ^ ((r >> 3) & 1):
+// any 8 consecutive rows use 8 different chunk slots (one 128-byte bank
+// sweep) and any 16 consecutive rows cover all 16 sixteen-byte slots of two
+// rows (one 256-byte sweep), so a fragment read of 16 rows is conflict-free
+// whether the LDS serves 8 or 16 lanes of a 128-bit read per cycle.
+__device__ __forceinline__ int swz(int r, int c) { return (r * 128) + ((c ^ (r & 7) ^ ((r >> 3) & 1)) << 4); }
 
 // 16 bytes from global memory; `valid` (0..16) leading bytes are real, the
 // rest take `fill`.
-__device__ __attribute__((noinline)) uint4 load16_partial(const uint8_t *p, int valid, uint32_t fill)
+__device__ __forceinline__ uint4 load16_partial(const uint8_t *p, int valid, uint32_t fill)
 {
     uint32_t w[4] = {fill, fill, fill, fill};
     for (int b = 0; b < valid && b < 16; ++b) {
@@ -49,20 +55,6 @@ __device__ __attribute__((noinline)) uint4 load16_partial(const uint8_t *p, int 
         w[b / 4] |= (uint32_t)p[b] << (8 * (b % 4));
     }
     return make_uint4(w[0], w[1], w[2], w[3]);
-}
-
-__device__ __forceinline__ uint4 load16(const uint8_t *p, int valid, uint32_t fill)
-{
-    if (valid >= 16) return *reinterpret_cast<const uint4 *>(p);
-    return load16_partial(p, valid, fill);
-}
-
-// The same for a source whose rows need not be 16-byte aligned (compressed
-// rows of K/2 and K/8 bytes when K is not a multiple of 128).
-__device__ __forceinline__ uint4 load16_any(const uint8_t *p, int valid, uint32_t fill)
-{
-    if (valid >= 16 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) return *reinterpret_cast<const uint4 *>(p);
-    return load16_partial(p, valid, fill);
 }
 
 template <int FA, int FB>
@@ -89,8 +81,76 @@ __device__ __forceinline__ void store_out(const GemmParams &p, int i, int j, flo
     else reinterpret_cast<float *>(p.c)[off] = v;
 }
 
+// Stores the four accumulator values of a lane: (i, j + q) when ALONG_J,
+// else (i + q, j), q = 0..3; to the split-K workspace when splits > 1.
+template <bool ALONG_J>
+__device__ __forceinline__ void store4(const GemmParams &p, int i, int j, int split, const v4f &v)
+{
+    if (p.splits > 1) {
+        float *w = p.ws + (int64_t)split * p.M * p.N;
+        if (ALONG_J) {
+            if (i >= p.M) return;
+            if (j + 3 < p.N && (p.N % 4) == 0) {
+                *reinterpret_cast<float4 *>(w + (int64_t)i * p.N + j) = make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+                for (int q = 0; q < 4; ++q)
+                    if (j + q < p.N) w[(int64_t)i * p.N + j + q] = v[q];
+            }
+        } else {
+            if (j >= p.N) return;
+            for (int q = 0; q < 4; ++q)
+                if (i + q < p.M) w[(int64_t)(i + q) * p.N + j] = v[q];
+        }
+        return;
+    }
+    // Output columns are consecutive for (ALONG_J, not transposed) and for
+    // (along i, transposed).
+    const bool contiguous = ALONG_J ? !p.trans_out : p.trans_out;
+    const int row = ALONG_J ? (p.trans_out ? j : i) : (p.trans_out ? j : i);
+    const int col0 = ALONG_J ? (p.trans_out ? i : j) : (p.trans_out ? i : j);
+    if (contiguous) {
+        const int rows = p.trans_out ? p.N : p.M, cols = p.trans_out ? p.M : p.N;
+        if (row >= rows) return;
+        float o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int iq = ALONG_J ? i : i + q, jq = ALONG_J ? j + q : j;
+            const float si = p.si[p.si_per ? min(iq, p.M - 1) : 0], sj = p.sj[p.sj_per ? min(jq, p.N - 1) : 0];
+            o[q] = p.trans_out ? (v[q] * sj) * si : (v[q] * si) * sj;
+        }
+        const int64_t off = (int64_t)row * p.ldc + col0;
+        const bool vec = col0 + 3 < cols && (p.ldc % 4) == 0 && ((reinterpret_cast<uintptr_t>(p.c) & 15) == 0);
+        if (p.out_bf16) {
+            uint16_t *c = reinterpret_cast<uint16_t *>(p.c) + off;
+            if (vec) {
+                uint2 w;
+                w.x = (uint32_t)f32_to_bf16_rne(o[0]) | ((uint32_t)f32_to_bf16_rne(o[1]) << 16);
+                w.y = (uint32_t)f32_to_bf16_rne(o[2]) | ((uint32_t)f32_to_bf16_rne(o[3]) << 16);
+                *reinterpret_cast<uint2 *>(c) = w;
+            } else {
+                for (int q = 0; q < 4; ++q)
+                    if (col0 + q < cols) c[q] = f32_to_bf16_rne(o[q]);
+            }
+        } else {
+            float *c = reinterpret_cast<float *>(p.c) + off;
+            if (vec) *reinterpret_cast<float4 *>(c) = make_float4(o[0], o[1], o[2], o[3]);
+            else
+                for (int q = 0; q < 4; ++q)
+                    if (col0 + q < cols) c[q] = o[q];
+        }
+    } else {
+        for (int q = 0; q < 4; ++q) {
+            const int iq = ALONG_J ? i : i + q, jq = ALONG_J ? j + q : j;
+            if (iq < p.M && jq < p.N) store_out(p, iq, jq, v[q]);
+        }
+    }
+}
+
 // Computes tile (tm, tn) of split `split`.  smem: TileSmem<BM,BN,SP>::TOTAL bytes.
-template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP>
+// KFAST: K is a multiple of 16 (dense) or 128 (compressed operand), so every
+// 16-byte chunk is either wholly inside the operand or wholly outside.
+// PF: prefetch depth, 2 (two register sets, loads two steps ahead) or 1.
+template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool KFAST = true, int PF = 2>
 __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
 {
     constexpr int NT = WM * WN * 64;
@@ -115,9 +175,17 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
     const int nk = (kend - kbeg + kBK - 1) / kBK;
     const int Kv = p.K / 2, Km = p.K / 8;   // compressed row lengths
 
-    uint4 ra[A_PER], rb[B_PER], rm[M_PER > 0 ? M_PER : 1];
+    uint4 ra[PF][A_PER], rb[PF][B_PER], rm[PF][M_PER > 0 ? M_PER : 1];
 
-    auto gload = [&](int kt) {
+    // Whole 16-byte chunks are loaded unconditionally from clamped, always
+    // readable addresses; chunks past the end of K are zeroed (metadata:
+    // given a valid filler) when the registers are written to LDS, after the
+    // MFMAs of the step, so the loads stay in flight across them.  Rows past
+    // M or N read row 0: they only feed outputs that are never stored.  Only
+    // a K that is not a multiple of 16 (128 for compressed rows) takes the
+    // exact byte path instead.
+    constexpr bool kfast = KFAST;
+    auto gload = [&](int kt, uint4 *ra, uint4 *rb, uint4 *rm) {
         const int k0 = kbeg + kt * kBK;
 #pragma unroll
         for (int u = 0; u < A_PER; ++u) {
@@ -127,14 +195,16 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
                 const int r = idx >> 2, c = idx & 3;
                 const int row = m0 + r;
                 const int vk = k0 / 2 + c * 16;
-                const int valid = row < p.M ? min(16, max(0, Kv - vk)) : 0;
-                ra[u] = load16_any(p.a + (int64_t)(row < p.M ? row : 0) * p.lda + (valid > 0 ? vk : 0), valid, 0u);
+                const uint8_t *src = p.a + (int64_t)(row < p.M ? row : 0) * p.lda;
+                if constexpr (kfast) ra[u] = *reinterpret_cast<const uint4 *>(src + (vk < Kv ? vk : 0));
+                else ra[u] = load16_partial(src + vk, row < p.M ? min(16, max(0, Kv - vk)) : 0, 0u);
             } else {
                 const int r = idx >> 3, c = idx & 7;
                 const int row = m0 + r;
                 const int kk = k0 + c * 16;
-                const int valid = row < p.M ? min(16, max(0, kend - kk)) : 0;
-                ra[u] = load16(p.a + (int64_t)(row < p.M ? row : 0) * p.lda + (valid > 0 ? kk : 0), valid, 0u);
+                const uint8_t *src = p.a + (int64_t)(row < p.M ? row : 0) * p.lda;
+                if constexpr (kfast) ra[u] = *reinterpret_cast<const uint4 *>(src + (kk < kend ? kk : 0));
+                else ra[u] = load16_partial(src + kk, row < p.M ? min(16, max(0, kend - kk)) : 0, 0u);
             }
         }
         if constexpr (SP) {
@@ -144,9 +214,9 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
                 if (r < M_CH) {
                     const int row = m0 + r;
                     const int mk = k0 / 8;
-                    const int valid = row < p.M ? min(16, max(0, Km - mk)) : 0;
-                    rm[u] = load16_any(p.meta + (int64_t)(row < p.M ? row : 0) * p.ldm + (valid > 0 ? mk : 0), valid,
-                                   0x44444444u);
+                    const uint8_t *src = p.meta + (int64_t)(row < p.M ? row : 0) * p.ldm;
+                    if constexpr (kfast) rm[u] = *reinterpret_cast<const uint4 *>(src + (mk < Km ? mk : 0));
+                    else rm[u] = load16_partial(src + mk, row < p.M ? min(16, max(0, Km - mk)) : 0, 0x44444444u);
                 }
             }
         }
@@ -157,29 +227,38 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
             const int r = idx >> 3, c = idx & 7;
             const int row = n0 + r;
             const int kk = k0 + c * 16;
-            const int valid = row < p.N ? min(16, max(0, kend - kk)) : 0;
-            rb[u] = load16(p.b + (int64_t)(row < p.N ? row : 0) * p.ldb + (valid > 0 ? kk : 0), valid, 0u);
+            const uint8_t *src = p.b + (int64_t)(row < p.N ? row : 0) * p.ldb;
+            if constexpr (kfast) rb[u] = *reinterpret_cast<const uint4 *>(src + (kk < kend ? kk : 0));
+            else rb[u] = load16_partial(src + kk, row < p.N ? min(16, max(0, kend - kk)) : 0, 0u);
         }
     };
 
-    auto sstore = [&](int buf) {
+    auto sel = [](const uint4 &v, bool ok, uint32_t fill) {
+        return ok ? v : make_uint4(fill, fill, fill, fill);
+    };
+
+    auto sstore = [&](int buf, const uint4 *ra, const uint4 *rb, const uint4 *rm, int kt) {
+        const int k0 = kbeg + kt * kBK;
         uint8_t *base = smem + buf * S::STAGE;
 #pragma unroll
         for (int u = 0; u < A_PER; ++u) {
             const int idx = tid + u * NT;
             if (A_CH < NT && idx >= A_CH) break;
             if constexpr (SP) {
-                *reinterpret_cast<uint4 *>(base + idx * 16) = ra[u];
+                const int c = idx & 3;
+                *reinterpret_cast<uint4 *>(base + idx * 16) = kfast ? sel(ra[u], k0 / 2 + c * 16 < Kv, 0u) : ra[u];
             } else {
                 const int r = idx >> 3, c = idx & 7;
-                *reinterpret_cast<uint4 *>(base + swz(r, c)) = ra[u];
+                *reinterpret_cast<uint4 *>(base + swz(r, c)) = kfast ? sel(ra[u], k0 + c * 16 < kend, 0u) : ra[u];
             }
         }
         if constexpr (SP) {
 #pragma unroll
             for (int u = 0; u < M_PER; ++u) {
                 const int r = tid + u * NT;
-                if (r < M_CH) *reinterpret_cast<uint4 *>(base + S::A_BYTES + r * 16) = rm[u];
+                if (r < M_CH)
+                    *reinterpret_cast<uint4 *>(base + S::A_BYTES + r * 16) =
+                        kfast ? sel(rm[u], k0 / 8 < Km, 0x44444444u) : rm[u];
             }
         }
         uint8_t *bb = base + S::A_BYTES + S::M_BYTES;
@@ -188,7 +267,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
             const int idx = tid + u * NT;
             if (B_CH < NT && idx >= B_CH) break;
             const int r = idx >> 3, c = idx & 7;
-            *reinterpret_cast<uint4 *>(bb + swz(r, c)) = rb[u];
+            *reinterpret_cast<uint4 *>(bb + swz(r, c)) = kfast ? sel(rb[u], k0 + c * 16 < kend, 0u) : rb[u];
         }
     };
 
@@ -198,15 +277,9 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    if (nk > 0) {
-        gload(0);
-        sstore(0);
-        __syncthreads();
-    }
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload(kt + 1);
-        const uint8_t *base = smem + cur * S::STAGE;
+    // One K step of MFMAs on LDS buffer `buf`.
+    auto compute = [&](int buf) {
+        const uint8_t *base = smem + buf * S::STAGE;
         const uint8_t *bb = base + S::A_BYTES + S::M_BYTES;
         // B fragment chunks: the dense instruction pairs lane group g of A and
         // B on codes 32g .. 32g+31; the sparse one expects B lane group g to
@@ -234,29 +307,63 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
                 uint4 hi = *reinterpret_cast<const uint4 *>(base + swz(r, 2 * lg + 1));
                 v8i af = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
 #pragma unroll
-                for (int j = 0; j < TN; ++j) acc[i][j] = mfma_dense<FA, FB>(af, bf[j], acc[i][j]);
+                for (int j = 0; j < TN; ++j) acc[i][j] = mfma_dense<FB, FA>(bf[j], af, acc[i][j]);
             }
         }
-        if (kt + 1 < nk) sstore(cur ^ 1);
-        __syncthreads();
+    };
+
+    if constexpr (PF == 1) {
+        // Loads of step k+1 go to the single register set during step k.
+        if (nk > 0) {
+            gload(0, ra[0], rb[0], rm[0]);
+            sstore(0, ra[0], rb[0], rm[0], 0);
+            __syncthreads();
+        }
+        for (int kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk) gload(kt + 1, ra[0], rb[0], rm[0]);
+            compute(kt & 1);
+            if (kt + 1 < nk) sstore((kt + 1) & 1, ra[0], rb[0], rm[0], kt + 1);
+            __syncthreads();
+        }
+    } else {
+        // Step k uses LDS buffer k % 2 and register set k % 2; the loop body
+        // is written out for an even and an odd step so every register set
+        // is named statically.  Loads and LDS stores are unconditional (past
+        // the last step they read clamped, valid addresses and fill a buffer
+        // nobody reads), which keeps the wait counts exact: the stores of a
+        // step wait only for the loads issued a step earlier.
+        if (nk > 0) {
+            gload(0, ra[0], rb[0], rm[0]);
+            gload(1, ra[PF - 1], rb[PF - 1], rm[PF - 1]);
+            sstore(0, ra[0], rb[0], rm[0], 0);
+            __syncthreads();
+        }
+        for (int kt = 0; kt < nk; kt += 2) {
+            gload(kt + 2, ra[0], rb[0], rm[0]);
+            compute(0);
+            sstore(1, ra[PF - 1], rb[PF - 1], rm[PF - 1], kt + 1);
+            __syncthreads();
+            if (kt + 1 >= nk) break;
+            gload(kt + 3, ra[PF - 1], rb[PF - 1], rm[PF - 1]);
+            compute(1);
+            sstore(0, ra[0], rb[0], rm[0], kt + 2);
+            __syncthreads();
+        }
     }
 
-    // epilogue: lane holds rows 4*lg .. 4*lg+3 of column lr of each 16 x 16 accumulator
+    // Epilogue.  Dense accumulators were produced with the operands swapped
+    // (B rows in the MFMA A slot), so a lane holds four consecutive j = n of
+    // one i = m and writes them with one vector store; the 2:4 accumulators
+    // hold four consecutive i of one j, which are consecutive in memory when
+    // the output is stored transposed (compressed weight).
+    constexpr bool ALONG_J = !SP;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-            const int col = n0 + wn * WTN + j * 16 + lr;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * WTM + i * 16 + 4 * lg + r;
-                if (row < p.M && col < p.N) {
-                    if (p.splits > 1)
-                        p.ws[((int64_t)split * p.M + row) * p.N + col] = acc[i][j][r];
-                    else
-                        store_out(p, row, col, acc[i][j][r]);
-                }
-            }
+            const int ib = m0 + wm * WTM + i * 16 + (ALONG_J ? lr : 4 * lg);
+            const int jb = n0 + wn * WTN + j * 16 + (ALONG_J ? 4 * lg : lr);
+            store4<ALONG_J>(p, ib, jb, split, acc[i][j]);
         }
 }
 

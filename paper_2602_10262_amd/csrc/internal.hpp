@@ -36,6 +36,9 @@ struct TileDesc {
 int num_tiles();
 const TileDesc &tile_desc(int t);
 
+// Whether K avoids partial 16-byte chunks; otherwise launch_gemm uses the
+// 128 x 128 byte-exact kernel whatever the tile.
+bool k_is_fast(bool sparse, int K);
 hipError_t launch_gemm(int tile, int fa, int fb, bool sparse, const GemmParams &p, hipStream_t st);
 hipError_t launch_splitk_reduce(const GemmParams &p, hipStream_t st);
 
