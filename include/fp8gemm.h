@@ -254,6 +254,13 @@ typedef struct {
 
 typedef struct fp8_server fp8_server;
 fp8_status fp8_server_create(const fp8_server_config *cfg, fp8_server **srv);
+/* The same scheduler over a simulated executor, for testing admission and
+ * statistics without a GPU: nothing is launched or read; a request occupies
+ * its stream for launch_us + 2*M*N*K / (gflop_per_ms * 1e9) ms of wall time
+ * and requests on one stream run one after another.  Weights and requests
+ * may carry NULL device pointers.  Workspace needs are not modelled. */
+fp8_status fp8_server_create_simulated(const fp8_server_config *cfg, double gflop_per_ms, double launch_us,
+                                       fp8_server **srv);
 /* Registers a weight: dense (meta NULL: w is N x K codes) or 2:4 (w = values
  * N x K/2, meta N x K/8).  w_descale: N floats.  Buffers stay caller-owned. */
 fp8_status fp8_server_register_weight(fp8_server *srv, const uint8_t *w, const uint8_t *meta,

@@ -88,6 +88,7 @@ _SIGS = {
     "fp8_grouped_plan_info": [_P, _P, _P, _P],
     "fp8_grouped_plan_destroy": [_P],
     "fp8_server_create": [_P, _P],
+    "fp8_server_create_simulated": [_P, _D, _D, _P],
     "fp8_server_register_weight": [_P, _P, _P, _P, _I64, _I64, _I, _P],
     "fp8_server_submit": [_P, _P, _P],
     "fp8_server_poll": [_P, ctypes.c_uint64],
@@ -341,3 +342,114 @@ def fp8_validate(c, cref, sabs, K, stream=None) -> dict:
     o = out.cpu().tolist()
     return {"max_abs_err": o[0], "max_ratio": o[1], "normwise": (o[2] / o[3]) ** 0.5 if o[3] > 0 else o[2] ** 0.5,
             "over": int(o[4]), "ok": o[4] == 0}
+
+
+# ----------------------------------------------------------------- grouped --
+
+class GroupedPlan:
+    """Owns an fp8_grouped_plan; problems' buffers must outlive it."""
+
+    def __init__(self, problems, tile: int = -1, use_graph: bool = False):
+        arr = (GroupProblem * len(problems))(*problems)
+        self._h = ctypes.c_void_p(0)
+        _call("fp8_grouped_plan_create", ctypes.cast(arr, _P), len(problems), tile, int(use_graph),
+              ctypes.byref(self._h))
+        self._keep = problems
+
+    def run(self, stream=None):
+        _call("fp8_grouped_gemm", self._h, _stream(stream))
+
+    def info(self) -> dict:
+        t, n, g = ctypes.c_int(0), ctypes.c_int64(0), ctypes.c_int(0)
+        _call("fp8_grouped_plan_info", self._h, ctypes.byref(t), ctypes.byref(n), ctypes.byref(g))
+        return {"tile": t.value, "tiles": n.value, "workgroups": g.value}
+
+    def close(self):
+        if self._h:
+            load().fp8_grouped_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dense_problem(a, w_nk, a_descale, w_descale, c, a_fmt=FP8_E4M3, w_fmt=FP8_E4M3) -> GroupProblem:
+    g = gemm_args(_u8(a), _u8(w_nk), a_descale, w_descale, c, a_fmt, w_fmt)
+    return GroupProblem(0, g, Sparse24GemmArgs())
+
+
+def sparse_weight_problem(a, w_values, w_meta, a_descale, w_descale, c, a_fmt=FP8_E4M3, w_fmt=FP8_E4M3):
+    sa = sparse24_args(w_values, w_meta, _u8(a), FP8_SPARSE_B, a_descale, w_descale, c, w_fmt, a_fmt)
+    return GroupProblem(1, GemmArgs(), sa)
+
+
+# ------------------------------------------------------------------ server --
+
+class Server:
+    """Owns an fp8_server (HIP streams + scheduler thread, or simulated)."""
+
+    def __init__(self, hbm_budget_bytes: int, num_streams: int = 4, max_inflight: int = 0,
+                 simulated: bool = False, gflop_per_ms: float = 1000.0, launch_us: float = 10.0):
+        cfg = ServerConfig(hbm_budget_bytes, num_streams, max_inflight)
+        self._h = ctypes.c_void_p(0)
+        if simulated:
+            _call("fp8_server_create_simulated", ctypes.byref(cfg), gflop_per_ms, launch_us, ctypes.byref(self._h))
+        else:
+            _call("fp8_server_create", ctypes.byref(cfg), ctypes.byref(self._h))
+
+    def register_weight(self, w, meta, w_descale, N: int, K: int, fmt: int = FP8_E4M3) -> int:
+        wid = ctypes.c_int(0)
+        _call("fp8_server_register_weight", self._h, _ptr(w), _ptr(meta), _ptr(w_descale), N, K, fmt,
+              ctypes.byref(wid))
+        return wid.value
+
+    def submit(self, M: int, weight_id: int, x=None, c=None, c_type: int = FP8_OUT_BF16,
+               x_fmt: int = FP8_E4M3, arrival_time_s: float = -1.0, x_ptr: int | None = None,
+               c_ptr: int | None = None) -> int:
+        req = Request(M, weight_id, x_ptr if x_ptr is not None else _ptr(x),
+                      c_ptr if c_ptr is not None else _ptr(c), c_type, x_fmt, arrival_time_s)
+        t = ctypes.c_uint64(0)
+        _call("fp8_server_submit", self._h, ctypes.byref(req), ctypes.byref(t))
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        return load().fp8_server_poll(self._h, ticket)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> int:
+        st = load().fp8_server_wait(self._h, ticket, timeout_us)
+        if st not in (FP8_OK, FP8_ERR_TIMEOUT):
+            _check("fp8_server_wait", st)
+        return st
+
+    def latency_ms(self, ticket: int) -> float:
+        v = ctypes.c_double(0)
+        _call("fp8_server_latency", self._h, ticket, ctypes.byref(v))
+        return v.value
+
+    def drain(self):
+        _call("fp8_server_drain", self._h)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _call("fp8_server_stats_get", self._h, ctypes.byref(st))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        _call("fp8_server_reset_stats", self._h)
+
+    def now(self) -> float:
+        return load().fp8_server_now(self._h)
+
+    def close(self):
+        if self._h:
+            load().fp8_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -147,7 +147,8 @@ fp8_plan heuristic_plan(const GemmKey &k)
     else if (M <= 32) p.tile = 5;
     else if (M <= 64) p.tile = 7;
     else if (M <= 128 || N <= 128) p.tile = 0;
-    else p.tile = 1;
+    else if (M * N >= (int64_t)4096 * 4096) p.tile = N >= M ? 13 : 12;
+    else p.tile = 0;
     const TileDesc &t = tile_desc(p.tile);
     p.split_k = default_splits(cdiv(M, t.bm) * cdiv(N, t.bn), k.kk);
     return p;

@@ -38,24 +38,6 @@ __global__ void __launch_bounds__(WM *WN * 64, OCC) gemm_kernel(GemmParams p)
     gemm_tile<BM, BN, WM, WN, FA, FB, SP, KFAST, PF>(p, tm, tn, blockIdx.z, smem);
 }
 
-// Tile table: (BM, BN, WM, WN, workgroups per CU the registers are sized
-// for, prefetch depth in K steps).  Index = plan.tile.
-#define FP8_TILE_LIST(X)           \
-    X(0, 128, 128, 2, 2, 2, 2)     \
-    X(1, 256, 128, 2, 2, 1, 1)     \
-    X(2, 256, 256, 2, 2, 1, 1)     \
-    X(3, 64, 64, 1, 1, 8, 2)       \
-    X(4, 16, 64, 1, 1, 8, 2)       \
-    X(5, 32, 128, 1, 2, 4, 2)      \
-    X(6, 128, 256, 2, 2, 1, 1)     \
-    X(7, 64, 256, 1, 4, 2, 2)      \
-    X(8, 128, 16, 4, 1, 2, 2)      \
-    X(9, 256, 32, 4, 1, 2, 2)      \
-    X(10, 256, 256, 2, 4, 1, 1)    \
-    X(11, 256, 256, 4, 2, 1, 1)    \
-    X(12, 256, 128, 4, 2, 1, 2)    \
-    X(13, 128, 256, 2, 4, 1, 2)
-
 #define FP8_DESC(i, bm, bn, wm, wn, occ, pf) {bm, bn, wm * wn, 1},
 static const TileDesc kTiles[] = {FP8_TILE_LIST(FP8_DESC)};
 #undef FP8_DESC

@@ -29,6 +29,25 @@ namespace fp8k {
 
 constexpr int kBK = 128;
 
+// Tile table: (BM, BN, WM, WN, workgroups per CU the registers are sized
+// for, prefetch depth in K steps).  Index = plan.tile.
+#define FP8_TILE_LIST(X)           \
+    X(0, 128, 128, 2, 2, 2, 2)     \
+    X(1, 256, 128, 2, 2, 1, 2)     \
+    X(2, 256, 256, 2, 2, 1, 2)     \
+    X(3, 64, 64, 1, 1, 8, 2)       \
+    X(4, 16, 64, 1, 1, 8, 2)       \
+    X(5, 32, 128, 1, 2, 4, 2)      \
+    X(6, 128, 256, 2, 2, 1, 2)     \
+    X(7, 64, 256, 1, 4, 2, 2)      \
+    X(8, 128, 16, 4, 1, 2, 2)      \
+    X(9, 256, 32, 4, 1, 2, 2)      \
+    X(10, 256, 256, 2, 4, 1, 2)    \
+    X(11, 256, 256, 4, 2, 1, 2)    \
+    X(12, 256, 128, 4, 2, 1, 2)    \
+    X(13, 128, 256, 2, 4, 1, 2)
+
+
 template <int BM, int BN, bool SP>
 struct TileSmem {
     static constexpr int A_BYTES = SP ? BM * 64 : BM * 128;
@@ -150,7 +169,13 @@ __device__ __forceinline__ void store4(const GemmParams &p, int i, int j, int sp
 // KFAST: K is a multiple of 16 (dense) or 128 (compressed operand), so every
 // 16-byte chunk is either wholly inside the operand or wholly outside.
 // PF: prefetch depth, 2 (two register sets, loads two steps ahead) or 1.
-template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool KFAST = true, int PF = 2>
+// SWAP (dense only): run the MFMA with B rows in its A slot, so a lane ends
+// up with four consecutive j of one i (vector stores for a row-major output);
+// without it a lane holds four consecutive i of one j, which suits a
+// transposed output.  The 2:4 path never swaps (the compressed operand must
+// sit in the A slot).
+template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool KFAST = true, int PF = 2,
+          bool SWAP = !SP>
 __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
 {
     constexpr int NT = WM * WN * 64;
@@ -306,8 +331,13 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
                 uint4 lo = *reinterpret_cast<const uint4 *>(base + swz(r, 2 * lg));
                 uint4 hi = *reinterpret_cast<const uint4 *>(base + swz(r, 2 * lg + 1));
                 v8i af = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                if constexpr (SWAP) {
 #pragma unroll
-                for (int j = 0; j < TN; ++j) acc[i][j] = mfma_dense<FB, FA>(bf[j], af, acc[i][j]);
+                    for (int j = 0; j < TN; ++j) acc[i][j] = mfma_dense<FB, FA>(bf[j], af, acc[i][j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) acc[i][j] = mfma_dense<FA, FB>(af, bf[j], acc[i][j]);
+                }
             }
         }
     };
@@ -351,12 +381,12 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
         }
     }
 
-    // Epilogue.  Dense accumulators were produced with the operands swapped
-    // (B rows in the MFMA A slot), so a lane holds four consecutive j = n of
-    // one i = m and writes them with one vector store; the 2:4 accumulators
-    // hold four consecutive i of one j, which are consecutive in memory when
-    // the output is stored transposed (compressed weight).
-    constexpr bool ALONG_J = !SP;
+    // Epilogue.  With SWAP a lane holds four consecutive j of one i and a
+    // row-major output takes them in one vector store; otherwise it holds four
+    // consecutive i of one j, consecutive in memory when the output is stored
+    // transposed (compressed weight, or a dense weight-major problem).
+    static_assert(!(SP && SWAP), "the compressed operand must stay in the MFMA A slot");
+    constexpr bool ALONG_J = SWAP;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll

@@ -1,0 +1,83 @@
+"""The C ABI: the library loads without a GPU and exports every entry point
+include/fp8gemm.h declares; argument errors come back as status codes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2602_10262_amd as lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fp8gemm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(fp8_[a-z0-9_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ["fp8_gemm", "fp8_sparse24_prune_compress", "fp8_sparse24_gemm", "fp8_grouped_gemm",
+                     "fp8_server_create", "fp8_server_submit", "fp8_quantize"]:
+        assert required in names
+    assert len(names) >= 30
+
+
+def test_library_exports_every_declared_symbol():
+    L = lib.load()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(declared_functions()) <= set(lib._SIGS), "binding lacks a declared entry point"
+
+
+def test_argument_errors_are_status_codes_without_gpu():
+    L = lib.load()
+    args = lib.GemmArgs()
+    assert L.fp8_gemm(ctypes.byref(args), None, None, 0, None) == 2  # FP8_ERR_SHAPE: M = 0
+    args.M = args.N = args.K = 16
+    args.a_descale = args.b_descale = args.c = 256
+    args.ldc = 16
+    assert L.fp8_gemm(ctypes.byref(args), None, None, 0, None) == 1  # FP8_ERR_ARG: null A
+    assert b"null A" in L.fp8_last_error()
+    args.a = args.b = 4096 + 8         # misaligned
+    args.lda = args.ldb = 16
+    assert L.fp8_gemm(ctypes.byref(args), None, None, 0, None) == 3  # FP8_ERR_ALIGN
+    assert L.fp8_sparse24_prune_compress(4096, 0, 4, 12, 16, 4096, 4096, None, None) == 2  # K % 8
+    n = ctypes.c_size_t(0)
+    assert L.fp8_quantize_workspace_size(8, 8, 0, ctypes.byref(n)) == 0 and n.value == 4
+
+
+def test_plan_resolution_and_workspace_on_host():
+    L = lib.load()
+    args = lib.GemmArgs(16, 8192, 8192, 4096, 0, 8192, 4096, 0, 8192, 256, 1, 256, 1, 256, 1, 8192)
+    tile, split = lib.fp8_gemm_plan_resolve(args)
+    assert 0 <= tile < lib.fp8_num_tiles() and split >= 1
+    info = lib.fp8_tile_info(tile)
+    assert info["block_m"] >= 16
+    nbytes = ctypes.c_size_t(0)
+    assert L.fp8_gemm_workspace_size(ctypes.byref(args), None, ctypes.byref(nbytes)) == 0
+    assert nbytes.value == (split * 16 * 8192 * 4 if split > 1 else 0)
+    # explicit plan is honoured
+    assert lib.fp8_gemm_plan_resolve(args, (0, 3)) == (0, 3)
+    with pytest.raises(lib.Fp8Error):
+        lib.fp8_gemm_plan_resolve(args, (999, 1))
+
+
+def test_tuning_cache_roundtrip(tmp_path):
+    L = lib.load()
+    lib.fp8_tune_cache_clear()
+    p = tmp_path / "cache.jsonl"
+    p.write_text('{"mk": 8192, "nk": 8192, "kk": 8192, "fa": 0, "fb": 0, "out_bf16": 1, "si_per": 1, '
+                 '"sj_per": 1, "sparse": 0, "tile": 3, "split_k": 2, "us": 123.000}\n')
+    lib.fp8_tune_cache_load(str(p))
+    args = lib.GemmArgs(8192, 8192, 8192, 4096, 0, 8192, 4096, 0, 8192, 256, 1, 256, 1, 256, 1, 8192)
+    assert lib.fp8_gemm_plan_resolve(args) == (3, 2)
+    out = tmp_path / "out.jsonl"
+    lib.fp8_tune_cache_save(str(out))
+    assert '"tile": 3' in out.read_text()
+    lib.fp8_tune_cache_clear()
+    assert lib.fp8_gemm_plan_resolve(args) != (3, 2)
