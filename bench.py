@@ -29,6 +29,32 @@ sys.path.insert(0, ROOT)
 PEAK_FP8_TFLOPS = 5000.0          # MI355X dense FP8 MFMA
 PEAK_FP8_SPARSE_TFLOPS = 10000.0  # 2:4 dense-equivalent
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dense_gemm_8192_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2602_10262_amd", "csrc", f) for f in ("gemm_tile.hpp", "gemm.hip")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline GEMM from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a copy of known size), or None when that summary is missing
+    or was taken from different kernel sources."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        if kv.get("kernel_source_sha1") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -112,6 +138,215 @@ def bench_sparse(lib, qa, da, qb, db, iters, warmup, stream):
     }
 
 
+def bench_shape(lib, M, N, K, fa, stream, iters=20, tune=True, rotate=1, sparse_too=True):
+    """One configured shape: tuned dense and 2:4 (on the identical pruned A)
+    timings; B rotated over `rotate` copies so large caches cannot hold it."""
+    import torch
+    from paper_2602_10262_amd import synth
+    xa = torch.from_numpy(synth.normal_outliers(7, (M, K))).cuda()
+    qa, _, da = lib.fp8_quantize(xa, fa, lib.FP8_SCALE_ROW)
+    del xa
+    xb = torch.from_numpy(synth.normal_outliers(8, (N, K))).cuda()
+    qb, _, db = lib.fp8_quantize(xb, 0, lib.FP8_SCALE_ROW)
+    del xb
+    bs = [qb] + [qb.clone() for _ in range(rotate - 1)]
+    c = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+    res = {"M": M, "N": N, "K": K, "a_fmt": "E5M2" if fa else "E4M3"}
+    flops = 2.0 * M * N * K
+    byts = M * K + N * K + 2 * M * N
+    # dense on the pruned A (the same matrix the 2:4 kernel sees)
+    values, meta, _ = lib.fp8_sparse24_prune_compress(qa, fa, with_mask=False)
+    pruned = lib.fp8_sparse24_decompress(values, meta, K)
+    gargs = lib.gemm_args(pruned, qb, da, db, c, fa, 0)
+    if tune:
+        lib.fp8_tune_gemm(gargs, iters=3, stream=stream)
+    it = [0]
+
+    def dense():
+        lib.fp8_gemm(pruned, bs[it[0] % rotate], da, db, fa, 0, c=c, stream=stream)
+        it[0] += 1
+    for _ in range(3):
+        dense()
+    ms = time_events(dense, iters, stream)
+    res["dense_ms"] = ms
+    res["dense_tflops"] = flops / ms / 1e9
+    res["dense_frac_peak"] = res["dense_tflops"] / PEAK_FP8_TFLOPS
+    res["dense_gbs"] = byts / ms / 1e6
+    res["plan"] = lib.fp8_gemm_plan_resolve(gargs)
+    if sparse_too:
+        sargs = lib.sparse24_args(values, meta, qb, lib.FP8_SPARSE_A, da, db, c, fa, 0)
+        if tune:
+            lib.fp8_tune_sparse24_gemm(sargs, iters=3, stream=stream)
+
+        def sparse():
+            lib.fp8_sparse24_gemm(values, meta, bs[it[0] % rotate], lib.FP8_SPARSE_A, da, db, fa, 0, c=c,
+                                  stream=stream)
+            it[0] += 1
+        for _ in range(3):
+            sparse()
+        sms = time_events(sparse, iters, stream)
+        res["sparse_ms"] = sms
+        res["sparse_tflops_dense_equiv"] = flops / sms / 1e9
+        res["sparse_frac_2to4_peak"] = res["sparse_tflops_dense_equiv"] / PEAK_FP8_SPARSE_TFLOPS
+        res["speedup_2to4_vs_dense"] = ms / sms
+        # weight-side 2:4 (the serving form): C = A x B' with B compressed
+        wv, wm, _ = lib.fp8_sparse24_prune_compress(qb, 0, with_mask=False)
+        wargs = lib.sparse24_args(wv, wm, qa, lib.FP8_SPARSE_B, da, db, c, 0, fa)
+        if tune:
+            lib.fp8_tune_sparse24_gemm(wargs, iters=3, stream=stream)
+        wms = time_events(lambda: lib.fp8_sparse24_gemm(wv, wm, qa, lib.FP8_SPARSE_B, da, db, 0, fa, c=c,
+                                                        stream=stream), iters, stream)
+        res["weight_sparse_ms"] = wms
+        res["speedup_weight_2to4_vs_dense"] = ms / wms
+    return res
+
+
+def bench_grouped(lib, stream, seed=0, count=64):
+    """64 transformer-shaped problems in one persistent launch (graph
+    replay) against 64 plain launches of the same problems on one stream."""
+    import torch
+    from paper_2602_10262_amd import synth
+    rng = np.random.default_rng(seed)
+    pairs = [(4096, 4096), (14336, 4096), (4096, 14336), (12288, 4096)]
+    Ms = synth.log_uniform_int(rng, 1, 4096, count)
+    nk = [pairs[i] for i in rng.integers(0, 4, count)]
+    sparse = np.zeros(count, bool)
+    sparse[rng.permutation(count)[: count // 2]] = True
+    probs, keep, plain = [], [], []
+    flops = 0.0
+    wbytes = 0
+    L = lib.load()
+    sh = stream.cuda_stream
+    import ctypes
+    for i in range(count):
+        M, (N, K) = int(Ms[i]), nk[i]
+        xa = torch.from_numpy(synth.normal_outliers(1000 + i, (M, K))).cuda()
+        qa, _, da = lib.fp8_quantize(xa, 0, lib.FP8_SCALE_ROW)
+        w = torch.randn((N, K), device="cuda")
+        qw, _, dw = lib.fp8_quantize(w, 0, lib.FP8_SCALE_ROW)
+        del w, xa
+        c = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+        if sparse[i]:
+            v, m, _ = lib.fp8_sparse24_prune_compress(qw, 0, with_mask=False)
+            probs.append(lib.sparse_weight_problem(qa, v, m, da, dw, c))
+            args = lib.sparse24_args(v, m, qa, lib.FP8_SPARSE_B, da, dw, c)
+            ws, nb = lib._workspace("fp8_sparse24_gemm_workspace_size", ctypes.byref(args), None, "cuda")
+            plain.append((L.fp8_sparse24_gemm, args, ws, nb))
+            keep.append((qa, v, m, da, dw, c, ws))
+            wbytes += N * K * 5 // 8
+        else:
+            probs.append(lib.dense_problem(qa, qw, da, dw, c))
+            args = lib.gemm_args(qa, qw, da, dw, c)
+            ws, nb = lib._workspace("fp8_gemm_workspace_size", ctypes.byref(args), None, "cuda")
+            plain.append((L.fp8_gemm, args, ws, nb))
+            keep.append((qa, qw, da, dw, c, ws))
+            wbytes += N * K
+        flops += 2.0 * M * N * K
+    torch.cuda.synchronize()
+    refs = [(fn, ctypes.byref(a), None if ws is None else ws.data_ptr(), nb) for fn, a, ws, nb in plain]
+
+    def run_plain():
+        for fn, a, w, nb in refs:
+            fn(a, None, w, nb, sh)
+    res = {"problems": count, "flops": flops, "weight_bytes": wbytes,
+           "M": {"min": int(Ms.min()), "median": int(np.median(Ms)), "max": int(Ms.max())},
+           "sparse_problems": int(sparse.sum())}
+    # plain per-problem launches, issued straight through the C ABI
+    run_plain()
+    plain_ms = time_events(run_plain, 5, stream)
+    res["plain_ms"] = plain_ms
+    res["plain_tflops"] = flops / plain_ms / 1e9
+    best = None
+    for tile in (9, 12, 13, 0, 7):
+        plan = lib.GroupedPlan(probs, tile=tile, use_graph=True)
+        plan.run(stream)
+        ms = time_events(lambda: plan.run(stream), 5, stream)
+        res[f"grouped_ms_tile{tile}"] = ms
+        if best is None or ms < best[1]:
+            best = (tile, ms, plan.info())
+        plan.close()
+    res["grouped_tile"] = best[0]
+    res["grouped_info"] = best[2]
+    res["grouped_ms"] = best[1]
+    res["grouped_tflops"] = flops / best[1] / 1e9
+    res["speedup_vs_plain"] = plain_ms / best[1]
+    # rooflines of the drawn instance: each problem alone at its own bound,
+    # and all of them overlapped
+    f_g = 2.0 * Ms * np.array([n for n, _ in nk]) * np.array([k for _, k in nk])
+    peak = np.where(sparse, PEAK_FP8_SPARSE_TFLOPS, PEAK_FP8_TFLOPS) * 1e12
+    b_g = np.array([M * K + (N * K * 5 // 8 if sp else N * K) + 2 * M * N
+                    for M, (N, K), sp in zip(Ms, nk, sparse)], dtype=np.float64)
+    res["serial_roofline_ms"] = float(np.sum(np.maximum(f_g / peak, b_g / (PEAK_HBM_GBS * 1e9)))) * 1e3
+    res["overlapped_roofline_ms"] = float(max(np.sum(f_g / peak), np.sum(b_g) / (PEAK_HBM_GBS * 1e9))) * 1e3
+    return res
+
+
+def bench_served(lib, n_requests=20000, seed=0, rates=(0.5, 1.0, 1.5), budget=2 << 30, streams=4, slots=32):
+    """Poisson stream of dense / 2:4 GEMM requests through the server on
+    `streams` streams against the same arrivals served one at a time."""
+    import torch
+    from paper_2602_10262_amd import synth
+    rng = np.random.default_rng(seed)
+    sizes = [2048, 4096, 8192, 14336]
+    Mmax = 8192
+    # resident weights: one per (N, K, dense | 2:4)
+    weights = {}
+    for N in sizes:
+        for K in sizes:
+            w = torch.randn((N, K), device="cuda")
+            qw, _, dw = lib.fp8_quantize(w, 0, lib.FP8_SCALE_ROW)
+            del w
+            v, m, _ = lib.fp8_sparse24_prune_compress(qw, 0, with_mask=False)
+            weights[(N, K)] = (qw, v, m, dw)
+    pools = {K: torch.from_numpy(synth.uniform(seed, K, (Mmax, K))).cuda() for K in sizes}
+    out_slots = [torch.empty(Mmax * max(sizes), dtype=torch.bfloat16, device="cuda") for _ in range(slots)]
+    Ms = synth.log_uniform_int(rng, 1, Mmax, n_requests)
+    Ns = rng.choice(sizes, n_requests)
+    Ks = rng.choice(sizes, n_requests)
+    sp = rng.random(n_requests) < 0.5
+    offs = [int(rng.integers(0, Mmax - M + 1)) for M in Ms]
+    flops = float(np.sum(2.0 * Ms * Ns * Ks))
+
+    def run(arrivals, nstreams, max_inflight):
+        srv = lib.Server(budget, nstreams, max_inflight)
+        ids = {}
+        for (N, K), (qw, v, m, dw) in weights.items():
+            ids[(N, K, False)] = srv.register_weight(qw, None, dw, N, K)
+            ids[(N, K, True)] = srv.register_weight(v, m, dw, N, K)
+        t0 = srv.now() + 0.05
+        tickets = []
+        for r in range(n_requests):
+            M, N, K = int(Ms[r]), int(Ns[r]), int(Ks[r])
+            x_ptr = pools[K].data_ptr() + offs[r] * K * 4
+            tickets.append(srv.submit(M, ids[(N, K, bool(sp[r]))], x_ptr=x_ptr,
+                                      c_ptr=out_slots[r % slots].data_ptr(),
+                                      arrival_time_s=t0 + float(arrivals[r])))
+        srv.drain()
+        st = srv.stats()
+        srv.close()
+        return st
+
+    # serial capacity: all requests present at once, one at a time
+    cap = run(np.zeros(n_requests), 1, 1)
+    mu = n_requests / cap["span_s"]
+    res = {"requests": n_requests, "flops": flops, "serial_capacity_req_s": mu,
+           "serial_capacity_tflops": cap["tflops"], "streams": streams, "budget_bytes": budget, "rates": []}
+    for f in rates:
+        lam = f * mu
+        arr = synth.poisson_arrivals(np.random.default_rng(seed + 1), lam, n_requests)
+        served = run(arr, streams, 4 * streams)
+        serial = run(arr, 1, 1)
+        keys = ("p50_ms", "p99_ms", "mean_ms", "tflops", "stream_cv", "fairness_range", "fairness_minmax",
+                "peak_inflight", "peak_bytes", "done")
+        res["rates"].append({"load": f, "rate_req_s": lam,
+                             "served": {k: served[k] for k in keys},
+                             "serial": {k: serial[k] for k in keys}})
+        log(f"served load {f}: p50 {served['p50_ms']:.2f} ms p99 {served['p99_ms']:.2f} ms "
+            f"{served['tflops']:.0f} TF/s | serial p50 {serial['p50_ms']:.2f} p99 {serial['p99_ms']:.2f} "
+            f"{serial['tflops']:.0f} TF/s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +356,11 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline GEMM, 2:4 and quantize only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default plan")
+    ap.add_argument("--sweep", action="store_true", help="also the square and skinny sweep with 2:4 break-even")
+    ap.add_argument("--requests", type=int, default=20000, help="served stream length")
+    ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only launch the headline GEMM 3 times and a 1 GiB device copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -131,8 +371,21 @@ def main():
     import paper_2602_10262_amd as lib
     lib.load()
     torch.cuda.init()
-    stream = torch.cuda.current_stream()
+    # a stream of our own: the grouped leg captures a HIP graph on it
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
     M = N = K = args.size
+    if args.traffic_probe:
+        xa, xb, qa, da, qb, db = make_operands(lib, M, N, K, 0)
+        c = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+        for _ in range(3):
+            lib.fp8_gemm(qa, qb, da, db, c=c, stream=stream)
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"traffic probe done; kernel_source_sha1: {kernel_source_hash()}", flush=True)
+        return
     log(f"bench: dense FP8 GEMM {M}x{N}x{K}")
     xa, xb, qa, da, qb, db = make_operands(lib, M, N, K, 0)
     c = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
@@ -171,7 +424,30 @@ def main():
     extra["sparse24"] = bench_sparse(lib, qa, da, qb, db, max(5, args.steps // 2), 3, stream)
     log(f"2:4: {extra['sparse24']['sparse_tflops_dense_equiv']:.1f} TFLOP/s dense-equivalent, "
         f"{extra['sparse24']['speedup_vs_dense']:.2f}x vs dense on the pruned matrix")
-    del xa, xb
+    del xa, xb, c
+    torch.cuda.empty_cache()
+
+    if not args.quick:
+        log("grouped: 64 problems ...")
+        extra["grouped"] = bench_grouped(lib, stream)
+        log(f"grouped {extra['grouped']['grouped_tflops']:.0f} TF/s vs plain {extra['grouped']['plain_tflops']:.0f}")
+        torch.cuda.empty_cache()
+        log("served stream ...")
+        extra["served"] = bench_served(lib, n_requests=args.requests)
+        torch.cuda.empty_cache()
+        # skinny shapes of the sweep (HBM-bound), B rotated past the caches
+        extra["skinny"] = [bench_shape(lib, m, 8192, 8192, 0, stream, rotate=5) for m in (16, 64, 256)]
+    if args.sweep:
+        sweep = []
+        for S in (1024, 2048, 4096, 8192, 16384):
+            for fa in (0, 1):
+                log(f"sweep {S}^3 fa={fa}")
+                sweep.append(bench_shape(lib, S, S, S, fa, stream))
+                torch.cuda.empty_cache()
+        for m in (16, 64, 256):
+            sweep.append(bench_shape(lib, m, 8192, 8192, 1, stream, rotate=5))
+        sweep.append(bench_shape(lib, 512, 2048, 1024, 0, stream))
+        extra["sweep"] = sweep
 
     out = {
         "metric": "FP8 TFLOP/s (% of peak) dense vs 2:4 sparse; grouped-serving p50/p99 latency",
@@ -190,13 +466,17 @@ def main():
                                "descales, FP32 accumulate, BF16 out", "M": M, "N": N, "K": K,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP8_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP8_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP8_TFLOPS, "traffic": measured_traffic() if M == 8192 else None},
         "extra": extra,
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(M, N, K)
-    print(json.dumps(out), flush=True)
+    line = json.dumps(out)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+    print(line, flush=True)
 
 
 if __name__ == "__main__":
