@@ -32,7 +32,7 @@ __device__ __forceinline__ void tile_coords(int M, int N, int &tm, int &tn)
 template <int BM, int BN, int WM, int WN, int OCC, int PF, int FA, int FB, bool SP, bool KFAST>
 __global__ void __launch_bounds__(WM *WN * 64, OCC) gemm_kernel(GemmParams p)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t smem[TileSmem<BM, BN, SP>::TOTAL];
+    __shared__ __attribute__((aligned(16))) uint8_t smem[TileSmem<BM, BN, SP, PF>::TOTAL];
     int tm, tn;
     tile_coords<BM, BN>(p.M, p.N, tm, tn);
     gemm_tile<BM, BN, WM, WN, FA, FB, SP, KFAST, PF>(p, tm, tn, blockIdx.z, smem);

@@ -28,13 +28,31 @@
 namespace fp8k {
 
 constexpr int kBK = 128;
+// Buffer resource word 3 for raw (unswizzled, unformatted) dword access on gfx9.
+constexpr int kBufferFlags = 0x00020000;
+
+template <int V>
+struct Int {
+    static constexpr int value = V;
+};
+
+// Calls f(Int<I>{}) for I = B .. E-1 with compile-time indices (keeps arrays
+// indexed by them in registers whatever the unroller decides).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(Int<B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 // Tile table: (BM, BN, WM, WN, workgroups per CU the registers are sized
 // for, prefetch depth in K steps).  Index = plan.tile.
 #define FP8_TILE_LIST(X)           \
     X(0, 128, 128, 2, 2, 2, 2)     \
     X(1, 256, 128, 2, 2, 1, 2)     \
-    X(2, 256, 256, 2, 2, 1, 2)     \
+    X(2, 256, 256, 2, 2, 1, 1)     \
     X(3, 64, 64, 1, 1, 8, 2)       \
     X(4, 16, 64, 1, 1, 8, 2)       \
     X(5, 32, 128, 1, 2, 4, 2)      \
@@ -42,20 +60,31 @@ constexpr int kBK = 128;
     X(7, 64, 256, 1, 4, 2, 2)      \
     X(8, 128, 16, 4, 1, 2, 2)      \
     X(9, 256, 32, 4, 1, 2, 2)      \
-    X(10, 256, 256, 2, 4, 1, 2)    \
+    X(10, 256, 256, 2, 4, 1, 1)    \
     X(11, 256, 256, 4, 2, 1, 2)    \
     X(12, 256, 128, 4, 2, 1, 2)    \
-    X(13, 128, 256, 2, 4, 1, 2)
+    X(13, 128, 256, 2, 4, 1, 2)    \
+    X(14, 128, 256, 2, 4, 1, 3)    \
+    X(15, 256, 128, 4, 2, 1, 3)    \
+    X(16, 128, 128, 2, 2, 1, 3)
 
 
-template <int BM, int BN, bool SP>
+// LDS of one tile: NSTAGE stages (2 for the register-prefetch loops, 3 for
+// the loop that also prefetches fragments).
+template <int BM, int BN, bool SP, int PF = 2>
 struct TileSmem {
     static constexpr int A_BYTES = SP ? BM * 64 : BM * 128;
     static constexpr int M_BYTES = SP ? BM * 16 : 0;
     static constexpr int B_BYTES = BN * 128;
     static constexpr int STAGE = A_BYTES + M_BYTES + B_BYTES;
-    static constexpr int TOTAL = 2 * STAGE;
+    static constexpr int NSTAGE = PF == 3 ? 3 : 2;
+    static constexpr int TOTAL = NSTAGE * STAGE;
 };
+
+// Compressed rows (64 value bytes) keep their 16-byte chunk c at c ^ h(r),
+// h(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1): the 16 rows a fragment read touches
+// land on 16 different 16-byte bank groups (and any 8 consecutive rows on 8).
+__device__ __forceinline__ int swz_sp(int r, int c) { return r * 64 + ((c ^ ((r >> 1) & 3) ^ ((r >> 3) & 1)) << 4); }
 
 // Chunk c of tile row r sits at chunk c ^ g(r), g(r) = (r & 7) ^ ((r >> 3) & 1):
 // any 8 consecutive rows use 8 different chunk slots (one 128-byte bank
@@ -168,7 +197,8 @@ __device__ __forceinline__ void store4(const GemmParams &p, int i, int j, int sp
 // Computes tile (tm, tn) of split `split`.  smem: TileSmem<BM,BN,SP>::TOTAL bytes.
 // KFAST: K is a multiple of 16 (dense) or 128 (compressed operand), so every
 // 16-byte chunk is either wholly inside the operand or wholly outside.
-// PF: prefetch depth, 2 (two register sets, loads two steps ahead) or 1.
+// PF: pipeline.  2: two register sets, global loads two steps ahead; 1: one
+// step ahead; 3: three LDS stages and fragments read one step ahead.
 // SWAP (dense only): run the MFMA with B rows in its A slot, so a lane ends
 // up with four consecutive j of one i (vector stores for a row-major output);
 // without it a lane holds four consecutive i of one j, which suits a
@@ -181,7 +211,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
     constexpr int NT = WM * WN * 64;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
-    using S = TileSmem<BM, BN, SP>;
+    using S = TileSmem<BM, BN, SP, PF>;
     constexpr int A_CH = SP ? BM * 4 : BM * 8;     // 16-byte chunks per stage
     constexpr int M_CH = SP ? BM : 0;
     constexpr int B_CH = BN * 8;
@@ -202,16 +232,50 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
 
     uint4 ra[PF][A_PER], rb[PF][B_PER], rm[PF][M_PER > 0 ? M_PER : 1];
 
-    // Whole 16-byte chunks are loaded unconditionally from clamped, always
-    // readable addresses; chunks past the end of K are zeroed (metadata:
-    // given a valid filler) when the registers are written to LDS, after the
-    // MFMAs of the step, so the loads stay in flight across them.  Rows past
-    // M or N read row 0: they only feed outputs that are never stored.  Only
-    // a K that is not a multiple of 16 (128 for compressed rows) takes the
-    // exact byte path instead.
+    // Chunks past the end of K are zeroed (metadata: given a valid filler)
+    // when the registers are written to LDS, after the MFMAs of the step, so
+    // the loads stay in flight across them.  Only a K that is not a multiple
+    // of 16 (128 for compressed rows) takes the exact byte path instead.
     constexpr bool kfast = KFAST;
+    // Fast path: buffer loads against per-tile resources whose range ends at
+    // the last valid row, so rows past M or N read as zero and no access
+    // leaves the operand; each thread needs one 32-bit offset per operand
+    // and every further chunk is a uniform (scalar) offset from it.
+    const int rows_a = min(BM, p.M - m0), rows_b = min(BN, p.N - n0);
+    const __amdgpu_buffer_rsrc_t rs_a = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(p.a + (int64_t)m0 * p.lda), (short)0, rows_a * (int)p.lda, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rs_b = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(p.b + (int64_t)n0 * p.ldb), (short)0, rows_b * (int)p.ldb, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rs_m = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(SP ? p.meta + (int64_t)m0 * p.ldm : p.a), (short)0, SP ? rows_a * (int)p.ldm : 0, kBufferFlags);
+    const int voff_a = SP ? (tid >> 2) * (int)p.lda + (tid & 3) * 16 : (tid >> 3) * (int)p.lda + (tid & 7) * 16;
+    const int voff_b = (tid >> 3) * (int)p.ldb + (tid & 7) * 16;
+    const int voff_m = tid * (int)p.ldm;
+    auto bload = [](const __amdgpu_buffer_rsrc_t &r, int voff, int soff) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    };
     auto gload = [&](int kt, uint4 *ra, uint4 *rb, uint4 *rm) {
         const int k0 = kbeg + kt * kBK;
+        if constexpr (kfast) {
+#pragma unroll
+            for (int u = 0; u < A_PER; ++u) {
+                if (A_CH < NT && tid + u * NT >= A_CH) break;
+                ra[u] = SP ? bload(rs_a, voff_a, u * (NT / 4) * (int)p.lda + k0 / 2)
+                           : bload(rs_a, voff_a, u * (NT / 8) * (int)p.lda + k0);
+            }
+            if constexpr (SP) {
+#pragma unroll
+                for (int u = 0; u < M_PER; ++u)
+                    if (tid + u * NT < M_CH) rm[u] = bload(rs_m, voff_m, u * NT * (int)p.ldm + k0 / 8);
+            }
+#pragma unroll
+            for (int u = 0; u < B_PER; ++u) {
+                if (B_CH < NT && tid + u * NT >= B_CH) break;
+                rb[u] = bload(rs_b, voff_b, u * (NT / 8) * (int)p.ldb + k0);
+            }
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < A_PER; ++u) {
             const int idx = tid + u * NT;
@@ -221,15 +285,13 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
                 const int row = m0 + r;
                 const int vk = k0 / 2 + c * 16;
                 const uint8_t *src = p.a + (int64_t)(row < p.M ? row : 0) * p.lda;
-                if constexpr (kfast) ra[u] = *reinterpret_cast<const uint4 *>(src + (vk < Kv ? vk : 0));
-                else ra[u] = load16_partial(src + vk, row < p.M ? min(16, max(0, Kv - vk)) : 0, 0u);
+                ra[u] = load16_partial(src + vk, row < p.M ? min(16, max(0, Kv - vk)) : 0, 0u);
             } else {
                 const int r = idx >> 3, c = idx & 7;
                 const int row = m0 + r;
                 const int kk = k0 + c * 16;
                 const uint8_t *src = p.a + (int64_t)(row < p.M ? row : 0) * p.lda;
-                if constexpr (kfast) ra[u] = *reinterpret_cast<const uint4 *>(src + (kk < kend ? kk : 0));
-                else ra[u] = load16_partial(src + kk, row < p.M ? min(16, max(0, kend - kk)) : 0, 0u);
+                ra[u] = load16_partial(src + kk, row < p.M ? min(16, max(0, kend - kk)) : 0, 0u);
             }
         }
         if constexpr (SP) {
@@ -240,8 +302,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
                     const int row = m0 + r;
                     const int mk = k0 / 8;
                     const uint8_t *src = p.meta + (int64_t)(row < p.M ? row : 0) * p.ldm;
-                    if constexpr (kfast) rm[u] = *reinterpret_cast<const uint4 *>(src + (mk < Km ? mk : 0));
-                    else rm[u] = load16_partial(src + mk, row < p.M ? min(16, max(0, Km - mk)) : 0, 0x44444444u);
+                    rm[u] = load16_partial(src + mk, row < p.M ? min(16, max(0, Km - mk)) : 0, 0x44444444u);
                 }
             }
         }
@@ -253,8 +314,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
             const int row = n0 + r;
             const int kk = k0 + c * 16;
             const uint8_t *src = p.b + (int64_t)(row < p.N ? row : 0) * p.ldb;
-            if constexpr (kfast) rb[u] = *reinterpret_cast<const uint4 *>(src + (kk < kend ? kk : 0));
-            else rb[u] = load16_partial(src + kk, row < p.N ? min(16, max(0, kend - kk)) : 0, 0u);
+            rb[u] = load16_partial(src + kk, row < p.N ? min(16, max(0, kend - kk)) : 0, 0u);
         }
     };
 
@@ -270,8 +330,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
             const int idx = tid + u * NT;
             if (A_CH < NT && idx >= A_CH) break;
             if constexpr (SP) {
-                const int c = idx & 3;
-                *reinterpret_cast<uint4 *>(base + idx * 16) = kfast ? sel(ra[u], k0 / 2 + c * 16 < Kv, 0u) : ra[u];
+                const int r = idx >> 2, c = idx & 3;
+                *reinterpret_cast<uint4 *>(base + swz_sp(r, c)) = kfast ? sel(ra[u], k0 / 2 + c * 16 < Kv, 0u) : ra[u];
             } else {
                 const int r = idx >> 3, c = idx & 7;
                 *reinterpret_cast<uint4 *>(base + swz(r, c)) = kfast ? sel(ra[u], k0 + c * 16 < kend, 0u) : ra[u];
@@ -322,7 +382,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
         for (int i = 0; i < TM; ++i) {
             const int r = wm * WTM + i * 16 + lr;
             if constexpr (SP) {
-                uint4 v = *reinterpret_cast<const uint4 *>(base + r * 64 + lg * 16);
+                uint4 v = *reinterpret_cast<const uint4 *>(base + swz_sp(r, lg));
                 const int idx = *reinterpret_cast<const int *>(base + S::A_BYTES + r * 16 + lg * 4);
                 v4i af = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
 #pragma unroll
@@ -342,7 +402,95 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
         }
     };
 
-    if constexpr (PF == 1) {
+    if constexpr (PF == 3) {
+        // Three LDS stages.  The B fragments and the first A fragment of step
+        // k+1 are read from LDS into a second register set while the MFMAs
+        // of step k run, so after each barrier a wave starts its MFMAs at
+        // once; the other A fragments of a step are read from its own stage
+        // while the previous row of MFMAs runs.  Step k: global loads of step
+        // k+2 -> registers; MFMAs of step k; fragments of step k+1 <- stage
+        // (k+1) % 3; registers -> stage (k+2) % 3 (last read during step
+        // k-1, before the barrier that ended it); barrier.
+        auto read_b = [&](int buf, v8i *gb) {
+            const uint8_t *bb = smem + buf * S::STAGE + S::A_BYTES + S::M_BYTES;
+            const int bc0 = SP ? lg : 2 * lg, bc1 = SP ? lg + 4 : 2 * lg + 1;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int r = wn * WTN + j * 16 + lr;
+                uint4 lo = *reinterpret_cast<const uint4 *>(bb + swz(r, bc0));
+                uint4 hi = *reinterpret_cast<const uint4 *>(bb + swz(r, bc1));
+                gb[j] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+        };
+        struct AFrag {
+            v8i d;
+            v4i s;
+            int idx;
+        };
+        auto read_a = [&](int buf, int i) {
+            const uint8_t *base = smem + buf * S::STAGE;
+            const int r = wm * WTM + i * 16 + lr;
+            AFrag f;
+            if constexpr (SP) {
+                uint4 v = *reinterpret_cast<const uint4 *>(base + swz_sp(r, lg));
+                f.idx = *reinterpret_cast<const int *>(base + S::A_BYTES + r * 16 + lg * 4);
+                f.s = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+            } else {
+                uint4 lo = *reinterpret_cast<const uint4 *>(base + swz(r, 2 * lg));
+                uint4 hi = *reinterpret_cast<const uint4 *>(base + swz(r, 2 * lg + 1));
+                f.d = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+            return f;
+        };
+        auto row_mma = [&](int i, const AFrag &f, const v8i *gb) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                if constexpr (SP) acc[i][j] = mfma_sparse<FA, FB>(f.s, gb[j], acc[i][j], f.idx);
+                else if constexpr (SWAP) acc[i][j] = mfma_dense<FB, FA>(gb[j], f.d, acc[i][j]);
+                else acc[i][j] = mfma_dense<FA, FB>(f.d, gb[j], acc[i][j]);
+            }
+        };
+        // MFMAs of the step held in stage `cur` (fragments gb, f0 already in
+        // registers), then the next step's fragments from stage `nxt`.
+        auto step = [&](int cur, const v8i *gb, const AFrag &f0, int nxt, v8i *nb, AFrag &n0) {
+            row_mma(0, f0, gb);
+#pragma unroll
+            for (int i = 1; i < TM; ++i) row_mma(i, read_a(cur, i), gb);
+            read_b(nxt, nb);
+            n0 = read_a(nxt, 0);
+        };
+        v8i gb0[TN], gb1[TN];
+        AFrag a0, a1;
+        int s0 = 0, s1 = 1, s2 = 2;   // stages of steps k, k+1, k+2
+        if (nk > 0) {
+            gload(0, ra[0], rb[0], rm[0]);
+            sstore(0, ra[0], rb[0], rm[0], 0);
+            gload(1, ra[0], rb[0], rm[0]);
+            sstore(1, ra[0], rb[0], rm[0], 1);
+            __syncthreads();
+            read_b(0, gb0);
+            a0 = read_a(0, 0);
+        }
+        auto rot = [&]() {
+            const int t = s0;
+            s0 = s1;
+            s1 = s2;
+            s2 = t;
+        };
+        for (int kt = 0; kt < nk; kt += 2) {
+            gload(kt + 2, ra[0], rb[0], rm[0]);
+            step(s0, gb0, a0, s1, gb1, a1);
+            sstore(s2, ra[0], rb[0], rm[0], kt + 2);
+            __syncthreads();
+            rot();
+            if (kt + 1 >= nk) break;
+            gload(kt + 3, ra[0], rb[0], rm[0]);
+            step(s0, gb1, a1, s1, gb0, a0);
+            sstore(s2, ra[0], rb[0], rm[0], kt + 3);
+            __syncthreads();
+            rot();
+        }
+    } else if constexpr (PF == 1) {
         // Loads of step k+1 go to the single register set during step k.
         if (nk > 0) {
             gload(0, ra[0], rb[0], rm[0]);
@@ -387,14 +535,15 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
     // transposed (compressed weight, or a dense weight-major problem).
     static_assert(!(SP && SWAP), "the compressed operand must stay in the MFMA A slot");
     constexpr bool ALONG_J = SWAP;
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
+    static_for<0, TM>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        static_for<0, TN>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
             const int ib = m0 + wm * WTM + i * 16 + (ALONG_J ? lr : 4 * lg);
             const int jb = n0 + wn * WTN + j * 16 + (ALONG_J ? 4 * lg : lr);
             store4<ALONG_J>(p, ib, jb, split, acc[i][j]);
-        }
+        });
+    });
 }
 
 }  // namespace fp8k

@@ -25,11 +25,11 @@ namespace fp8k {
 
 __global__ void grouped_reset(unsigned long long *counter) { *counter = 0ull; }
 
-template <int BM, int BN, int WM, int WN, int OCC, int FA, int FB>
+template <int BM, int BN, int WM, int WN, int OCC, int PF, int FA, int FB>
 __global__ void __launch_bounds__(WM *WN * 64, OCC)
     grouped_kernel(const GroupEntry *__restrict__ table, int count, int64_t total, unsigned long long *counter)
 {
-    constexpr int SMD = TileSmem<BM, BN, false>::TOTAL, SMS = TileSmem<BM, BN, true>::TOTAL;
+    constexpr int SMD = TileSmem<BM, BN, false, PF>::TOTAL, SMS = TileSmem<BM, BN, true, PF>::TOTAL;
     __shared__ __attribute__((aligned(16))) uint8_t smem[SMD > SMS ? SMD : SMS];
     __shared__ long long next;
     for (;;) {
@@ -49,13 +49,13 @@ __global__ void __launch_bounds__(WM *WN * 64, OCC)
         const int tiles_m = table[lo].tiles_m;
         const int tm = local % tiles_m, tn = local / tiles_m;
         if (table[lo].sparse)
-            gemm_tile<BM, BN, WM, WN, FA, FB, true, true, 2, false>(p, tm, tn, 0, smem);
+            gemm_tile<BM, BN, WM, WN, FA, FB, true, true, PF, false>(p, tm, tn, 0, smem);
         else
-            gemm_tile<BM, BN, WM, WN, FA, FB, false, true, 2, false>(p, tm, tn, 0, smem);
+            gemm_tile<BM, BN, WM, WN, FA, FB, false, true, PF, false>(p, tm, tn, 0, smem);
     }
 }
 
-template <int BM, int BN, int WM, int WN, int OCC>
+template <int BM, int BN, int WM, int WN, int OCC, int PF>
 static hipError_t grouped_one(int fa, int fb, const GroupEntry *table, int count, int64_t total, int *counter,
                               int grid, hipStream_t st)
 {
@@ -63,17 +63,17 @@ static hipError_t grouped_one(int fa, int fb, const GroupEntry *table, int count
     grouped_reset<<<1, 1, 0, st>>>(c);
     dim3 g((unsigned)grid), b(WM * WN * 64);
     switch (fa * 2 + fb) {
-    case 0: grouped_kernel<BM, BN, WM, WN, OCC, 0, 0><<<g, b, 0, st>>>(table, count, total, c); break;
-    case 1: grouped_kernel<BM, BN, WM, WN, OCC, 0, 1><<<g, b, 0, st>>>(table, count, total, c); break;
-    case 2: grouped_kernel<BM, BN, WM, WN, OCC, 1, 0><<<g, b, 0, st>>>(table, count, total, c); break;
-    default: grouped_kernel<BM, BN, WM, WN, OCC, 1, 1><<<g, b, 0, st>>>(table, count, total, c); break;
+    case 0: grouped_kernel<BM, BN, WM, WN, OCC, PF, 0, 0><<<g, b, 0, st>>>(table, count, total, c); break;
+    case 1: grouped_kernel<BM, BN, WM, WN, OCC, PF, 0, 1><<<g, b, 0, st>>>(table, count, total, c); break;
+    case 2: grouped_kernel<BM, BN, WM, WN, OCC, PF, 1, 0><<<g, b, 0, st>>>(table, count, total, c); break;
+    default: grouped_kernel<BM, BN, WM, WN, OCC, PF, 1, 1><<<g, b, 0, st>>>(table, count, total, c); break;
     }
     return hipGetLastError();
 }
 
 // Tiles the grouped kernel is compiled for (a subset of the tile table: the
 // weight-row x token shapes that suit transformer mixes).
-#define FP8_GROUP_TILES(X) X(0) X(3) X(7) X(8) X(9) X(12) X(13)
+#define FP8_GROUP_TILES(X) X(0) X(3) X(7) X(8) X(9) X(12) X(13) X(14) X(15)
 
 template <int T>
 struct TileArgs;
@@ -83,7 +83,7 @@ struct TileArgs;
         static hipError_t go(int fa, int fb, const GroupEntry *table, int count, int64_t total, \
                              int *counter, int grid, hipStream_t st)                   \
         {                                                                              \
-            return grouped_one<bm, bn, wm, wn, occ>(fa, fb, table, count, total, counter, grid, st); \
+            return grouped_one<bm, bn, wm, wn, occ, pf>(fa, fb, table, count, total, counter, grid, st); \
         }                                                                              \
     };
 FP8_TILE_LIST(FP8_TARGS)

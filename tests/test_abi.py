@@ -67,6 +67,14 @@ def test_plan_resolution_and_workspace_on_host():
         lib.fp8_gemm_plan_resolve(args, (999, 1))
 
 
+def test_gpu_tests_cover_every_tile():
+    from tests.test_gpu_gemm import NUM_TILES
+    assert lib.fp8_num_tiles() == NUM_TILES
+    for t in range(NUM_TILES):
+        info = lib.fp8_tile_info(t)
+        assert info["block_m"] % 16 == 0 and info["block_n"] % 16 == 0
+
+
 def test_tuning_cache_roundtrip(tmp_path):
     L = lib.load()
     lib.fp8_tune_cache_clear()

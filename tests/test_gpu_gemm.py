@@ -43,7 +43,10 @@ def test_dense_ragged_shapes(gpu, M, N, K, fa, bf16):
     check_gemm(c, qa, fa, qb, 0, da, db, bf16, f"{M}x{N}x{K}")
 
 
-@pytest.mark.parametrize("tile", list(range(10)))
+NUM_TILES = 17   # tile configurations the library exports (checked on the host)
+
+
+@pytest.mark.parametrize("tile", list(range(NUM_TILES)))
 @pytest.mark.parametrize("split", [1, 3])
 def test_every_tile_and_split(gpu, tile, split):
     M, N, K = 200, 300, 640
@@ -128,7 +131,7 @@ def test_sparse_B_weight(gpu, M, N, K, bf16):
     check_gemm(c, qa, 0, pw, 0, da, db, bf16, "sparse B")
 
 
-@pytest.mark.parametrize("tile", list(range(10)))
+@pytest.mark.parametrize("tile", list(range(NUM_TILES)))
 def test_sparse_every_tile(gpu, tile):
     import torch
     M, N, K = 150, 200, 512
