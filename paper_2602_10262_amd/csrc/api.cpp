@@ -152,9 +152,10 @@ fp8_plan heuristic_plan(const GemmKey &k)
     else if (M <= 32) p.tile = 5;
     else if (M <= 64) p.tile = 7;
     else if (M <= 128 || N <= 128) p.tile = 0;
-    // the 256 x 256 tile reads 25% less LDS per MFMA; with 2:4 operands it
-    // wins once there are enough tiles to fill the chip twice over
-    else if (k.sparse && M >= 4096 && N >= 4096) p.tile = 10;
+    // 256 x 256 with LDS DMA: 128 x 64 wave tiles read 25% less LDS per
+    // MFMA than 64 x 64 ones and no registers stage the loads; it wins once
+    // there are enough tiles to fill the chip
+    else if (M >= 4096 && N >= 4096 && (k.kk % 128) == 0) p.tile = 19;
     else if (M * N >= (int64_t)4096 * 4096) p.tile = N >= M ? 13 : 12;
     else p.tile = 0;
     const TileDesc &t = tile_desc(p.tile);

@@ -48,7 +48,7 @@ __device__ __forceinline__ void static_for(F &&f)
 }
 
 // Tile table: (BM, BN, WM, WN, workgroups per CU the registers are sized
-// for, prefetch depth in K steps).  Index = plan.tile.
+// for, pipeline PF as described at gemm_tile).  Index = plan.tile.
 #define FP8_TILE_LIST(X)           \
     X(0, 128, 128, 2, 2, 2, 2)     \
     X(1, 256, 128, 2, 2, 1, 2)     \
@@ -66,18 +66,22 @@ __device__ __forceinline__ void static_for(F &&f)
     X(13, 128, 256, 2, 4, 1, 2)    \
     X(14, 128, 256, 2, 4, 1, 3)    \
     X(15, 256, 128, 4, 2, 1, 3)    \
-    X(16, 128, 128, 2, 2, 1, 3)
+    X(16, 128, 128, 2, 2, 1, 3)    \
+    X(17, 256, 128, 2, 2, 1, 7)    \
+    X(18, 128, 256, 2, 2, 1, 7)    \
+    X(19, 256, 256, 2, 4, 1, 6)
 
 
-// LDS of one tile: NSTAGE stages (2 for the register-prefetch loops, 3 for
-// the loop that also prefetches fragments).
+// LDS of one tile: NSTAGE stages (2 for the register-prefetch loops and the
+// two-stage DMA loop, 3 for the loop that also prefetches fragments and for
+// the three-stage DMA loop).
 template <int BM, int BN, bool SP, int PF = 2>
 struct TileSmem {
     static constexpr int A_BYTES = SP ? BM * 64 : BM * 128;
     static constexpr int M_BYTES = SP ? BM * 16 : 0;
     static constexpr int B_BYTES = BN * 128;
     static constexpr int STAGE = A_BYTES + M_BYTES + B_BYTES;
-    static constexpr int NSTAGE = PF == 3 ? 3 : 2;
+    static constexpr int NSTAGE = (PF == 3 || PF == 7) ? 3 : 2;
     static constexpr int TOTAL = NSTAGE * STAGE;
 };
 
@@ -194,11 +198,217 @@ __device__ __forceinline__ void store4(const GemmParams &p, int i, int j, int sp
     }
 }
 
+// One 16-byte load per lane from a buffer resource straight into LDS: lane l
+// writes LDS bytes [lds + 16 l, lds + 16 l + 16).  Issued from inline
+// assembly so that the compiler does not treat the pending LDS write as a
+// possible alias of every later LDS read (which would make it wait for the
+// load before the fragment reads of the current stage); the caller waits for
+// these loads with wait_vm before the barrier that publishes the stage.
+// The instruction writes no register.  M0 carries the LDS address (bound as
+// an input, so the compiler writes it).  The scalar operands are wave-uniform
+// by construction; readfirstlane says so where the analysis cannot see it,
+// which may leave a VALU write of the scalar offset right before the load.
+// The compiler's hazard checks do not look inside the asm, so it waits the
+// five states a vector memory read of a VALU-written SGPR needs (which also
+// covers the one state after an M0 write).
+__device__ __forceinline__ void dma16(uint32_t lds, int voff, __amdgpu_buffer_rsrc_t rs, int soff)
+{
+    const uint32_t m = __builtin_amdgcn_readfirstlane(lds);
+    const int so = __builtin_amdgcn_readfirstlane(soff);
+    asm volatile("s_nop 4\n\tbuffer_load_dwordx4 %0, %1, %2 offen lds"
+                 :
+                 : "v"(voff), "s"(rs), "s"(so), "{m0}"(m)
+                 : "memory");
+}
+
+// s_waitcnt vmcnt(N) with the other counters left alone (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// LDS-DMA pipeline (PF 6: NS = 2 LDS stages, PF 7: NS = 3).  Global tiles go
+// straight from memory into LDS without passing through registers, which
+// frees the staging registers for larger wave tiles (a 128 x 128 wave tile
+// reads half the LDS bytes per MFMA of a 64 x 64 one).  Each 1 KiB block of
+// a stage is filled by one wave instruction; the lane that writes slot c' of
+// row r fetches global chunk c' ^ swizzle(r), so LDS holds the same swizzled
+// layout the fragment reads expect.  Chunks past the end of K are fetched
+// from an offset beyond the resource range, which the hardware returns as
+// zero.  Step k: wait for stage k (own loads), barrier (everyone's loads;
+// everyone done reading stage k - 1), issue stage k + NS - 1 into the buffer
+// of step k - 1, MFMAs of stage k.  One stage is issued per step whatever k
+// is (past the last step into a buffer nobody reads), so the wait count is a
+// constant; everything is drained before the workgroup ends.  Requires K to
+// be a multiple of 16 (dense) or 128 (compressed operand).
+template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, int NS, int PF, bool SWAP>
+__device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
+{
+    constexpr int NW = WM * WN;
+    constexpr int WTM = BM / WM, WTN = BN / WN;
+    constexpr int TM = WTM / 16, TN = WTN / 16;
+    using S = TileSmem<BM, BN, SP, PF>;
+    static_assert(S::NSTAGE == NS, "stage count");
+    static_assert(NW % 2 == 0, "the per-lane swizzle must not change between rounds");
+    constexpr int QA = S::A_BYTES / 1024, QM = S::M_BYTES / 1024, QB = S::B_BYTES / 1024;
+    static_assert(S::A_BYTES % 1024 == 0 && S::M_BYTES % 1024 == 0 && S::B_BYTES % 1024 == 0, "1 KiB blocks");
+    static_assert(QA % NW == 0 && QB % NW == 0 && (QM % NW == 0 || QM < NW), "blocks per wave");
+    constexpr int RA = QA / NW, RB = QB / NW, RM = QM / NW;   // rounds per wave per stage
+    constexpr int PER = RA + RB + RM;                          // DMA instructions per wave per stage (at least)
+    static_assert((NS - 2) * PER < 64, "vmcnt range");
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int kbeg = split * p.kchunk;
+    const int kend = min(p.K, kbeg + p.kchunk);
+    const int nk = (kend - kbeg + kBK - 1) / kBK;
+    const int Kv = p.K / 2, Km = p.K / 8;
+
+    const int rows_a = min(BM, p.M - m0), rows_b = min(BN, p.N - n0);
+    const int rec_a = rows_a * (int)p.lda, rec_b = rows_b * (int)p.ldb, rec_m = SP ? rows_a * (int)p.ldm : 0;
+    const __amdgpu_buffer_rsrc_t rs_a =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(p.a + (int64_t)m0 * p.lda), (short)0, rec_a, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rs_b =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(p.b + (int64_t)n0 * p.ldb), (short)0, rec_b, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rs_m = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(SP ? p.meta + (int64_t)m0 * p.ldm : p.a), (short)0, rec_m, kBufferFlags);
+
+    // Per-lane source of the first block a wave fills; later rounds move
+    // down by NW blocks (a whole number of rows, same swizzle phase).
+    // Dense rows (128 bytes): block q holds rows 8q .. 8q+7, lane l row
+    // 8q + l/8, slot l%8, so the source chunk is (l%8) ^ (l/8) ^ (q&1).
+    const int cd = (lane & 7) ^ (lane >> 3) ^ (wave & 1);
+    const int voff_b = (wave * 8 + (lane >> 3)) * (int)p.ldb + cd * 16;
+    // A: dense as B; compressed values (64 bytes): block q holds rows 16q ..
+    // 16q+15, lane l row 16q + l/4, slot l%4, chunk (l%4) ^ ((l>>3)&3) ^ (l>>5).
+    const int cs = (lane & 3) ^ ((lane >> 3) & 3) ^ (lane >> 5);
+    const int ca = SP ? cs : cd;
+    const int voff_a = SP ? (wave * 16 + (lane >> 2)) * (int)p.lda + cs * 16 : (wave * 8 + (lane >> 3)) * (int)p.lda + cd * 16;
+    // metadata (16 bytes per row): block q holds rows 64q .. 64q+63.
+    const int voff_m = (wave * 64 + lane) * (int)p.ldm;
+    const uint32_t lds0 = (uint32_t)(uintptr_t)smem;
+
+    auto issue = [&](int kt, int stage) {
+        const int k0 = kbeg + kt * kBK;
+        const uint32_t sb = lds0 + stage * S::STAGE;
+        // whole chunks past the end of K read as zero: point them past the range
+        const int va = SP ? (k0 / 2 + ca * 16 < Kv ? voff_a : rec_a) : (k0 + ca * 16 < kend ? voff_a : rec_a);
+        const int vb = k0 + cd * 16 < kend ? voff_b : rec_b;
+        static_for<0, RA>([&](auto uu) {
+            constexpr int u = decltype(uu)::value;
+            constexpr int rows = SP ? 16 : 8;
+            dma16(sb + (wave + u * NW) * 1024, va, rs_a, u * NW * rows * (int)p.lda + (SP ? k0 / 2 : k0));
+        });
+        if constexpr (SP) {
+            const int vm = k0 / 8 < Km ? voff_m : rec_m;
+            if constexpr (RM > 0) {
+                static_for<0, RM>([&](auto uu) {
+                    constexpr int u = decltype(uu)::value;
+                    dma16(sb + S::A_BYTES + (wave + u * NW) * 1024, vm, rs_m, u * NW * 64 * (int)p.ldm + k0 / 8);
+                });
+            } else {
+                if (wave < QM) dma16(sb + S::A_BYTES + wave * 1024, vm, rs_m, k0 / 8);
+            }
+        }
+        static_for<0, RB>([&](auto uu) {
+            constexpr int u = decltype(uu)::value;
+            dma16(sb + S::A_BYTES + S::M_BYTES + (wave + u * NW) * 1024, vb, rs_b, u * NW * 8 * (int)p.ldb + k0);
+        });
+    };
+
+    v4f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    // Fragment addresses: rows 16 apart share their swizzle phase, so every
+    // fragment of a wave is one per-lane base plus a compile-time offset
+    // (2048 bytes per 16 dense rows, 1024 per 16 compressed rows, 256 per
+    // 16 metadata rows).
+    const int rb0 = wn * WTN + lr, ra0 = wm * WTM + lr;
+    const int ob0 = S::A_BYTES + S::M_BYTES + swz(rb0, SP ? lg : 2 * lg);
+    const int ob1 = S::A_BYTES + S::M_BYTES + swz(rb0, SP ? lg + 4 : 2 * lg + 1);
+    const int oa0 = SP ? swz_sp(ra0, lg) : swz(ra0, 2 * lg);
+    const int oa1 = SP ? S::A_BYTES + ra0 * 16 + lg * 4 : swz(ra0, 2 * lg + 1);
+    auto compute = [&](int stage) {
+        const uint8_t *base = smem + stage * S::STAGE;
+        v8i bf[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            uint4 lo = *reinterpret_cast<const uint4 *>(base + ob0 + j * 2048);
+            uint4 hi = *reinterpret_cast<const uint4 *>(base + ob1 + j * 2048);
+            bf[j] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            if constexpr (SP) {
+                uint4 v = *reinterpret_cast<const uint4 *>(base + oa0 + i * 1024);
+                const int idx = *reinterpret_cast<const int *>(base + oa1 + i * 256);
+                v4i af = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = mfma_sparse<FA, FB>(af, bf[j], acc[i][j], idx);
+            } else {
+                uint4 lo = *reinterpret_cast<const uint4 *>(base + oa0 + i * 2048);
+                uint4 hi = *reinterpret_cast<const uint4 *>(base + oa1 + i * 2048);
+                v8i af = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    if constexpr (SWAP) acc[i][j] = mfma_dense<FB, FA>(bf[j], af, acc[i][j]);
+                    else acc[i][j] = mfma_dense<FA, FB>(af, bf[j], acc[i][j]);
+                }
+            }
+        }
+    };
+
+    if (nk > 0) {
+        static_for<0, NS - 1>([&](auto ss) {
+            constexpr int s = decltype(ss)::value;
+            issue(s, s);
+        });
+        // the body is written out NS times so every stage index is static
+        for (int kt = 0; kt < nk; kt += NS) {
+            bool done = false;
+            static_for<0, NS>([&](auto ss) {
+                constexpr int s = decltype(ss)::value;
+                if (done || kt + s >= nk) {
+                    done = true;
+                    return;
+                }
+                wait_vm<(NS - 2) * PER>();
+                __syncthreads();
+                issue(kt + s + NS - 1, (s + NS - 1) % NS);
+                compute(s);
+            });
+        }
+        wait_vm<0>();
+    }
+
+    static_assert(!(SP && SWAP), "the compressed operand must stay in the MFMA A slot");
+    constexpr bool ALONG_J = SWAP;
+    static_for<0, TM>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        static_for<0, TN>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            const int ib = m0 + wm * WTM + i * 16 + (ALONG_J ? lr : 4 * lg);
+            const int jb = n0 + wn * WTN + j * 16 + (ALONG_J ? 4 * lg : lr);
+            store4<ALONG_J>(p, ib, jb, split, acc[i][j]);
+        });
+    });
+}
+
 // Computes tile (tm, tn) of split `split`.  smem: TileSmem<BM,BN,SP>::TOTAL bytes.
 // KFAST: K is a multiple of 16 (dense) or 128 (compressed operand), so every
 // 16-byte chunk is either wholly inside the operand or wholly outside.
 // PF: pipeline.  2: two register sets, global loads two steps ahead; 1: one
-// step ahead; 3: three LDS stages and fragments read one step ahead.
+// step ahead; 3: three LDS stages and fragments read one step ahead; 6 / 7:
+// global -> LDS DMA with two / three LDS stages (gemm_tile_dma).
 // SWAP (dense only): run the MFMA with B rows in its A slot, so a lane ends
 // up with four consecutive j of one i (vector stores for a row-major output);
 // without it a lane holds four consecutive i of one j, which suits a
@@ -208,6 +418,11 @@ template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool KFAST = 
           bool SWAP = !SP>
 __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
 {
+    if constexpr (PF == 6 || PF == 7) {
+        static_assert(KFAST, "the DMA pipeline needs whole 16-byte chunks");
+        gemm_tile_dma<BM, BN, WM, WN, FA, FB, SP, PF == 6 ? 2 : 3, PF, SWAP>(p, tm, tn, split, smem);
+        return;
+    }
     constexpr int NT = WM * WN * 64;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 16, TN = WTN / 16;

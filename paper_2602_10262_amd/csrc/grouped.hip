@@ -73,7 +73,7 @@ static hipError_t grouped_one(int fa, int fb, const GroupEntry *table, int count
 
 // Tiles the grouped kernel is compiled for (a subset of the tile table: the
 // weight-row x token shapes that suit transformer mixes).
-#define FP8_GROUP_TILES(X) X(0) X(3) X(7) X(8) X(9) X(12) X(13) X(14) X(15)
+#define FP8_GROUP_TILES(X) X(0) X(3) X(7) X(8) X(9) X(12) X(13)
 
 template <int T>
 struct TileArgs;
