@@ -372,20 +372,14 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
             constexpr int s = decltype(ss)::value;
             issue(s, s);
         });
-        // the body is written out NS times so every stage index is static
-        for (int kt = 0; kt < nk; kt += NS) {
-            bool done = false;
-            static_for<0, NS>([&](auto ss) {
-                constexpr int s = decltype(ss)::value;
-                if (done || kt + s >= nk) {
-                    done = true;
-                    return;
-                }
-                wait_vm<(NS - 2) * PER>();
-                __syncthreads();
-                issue(kt + s + NS - 1, (s + NS - 1) % NS);
-                compute(s);
-            });
+        int st = 0, nx = NS - 1;   // stage of step kt, stage of step kt + NS - 1
+        for (int kt = 0; kt < nk; ++kt) {
+            wait_vm<(NS - 2) * PER>();
+            __syncthreads();
+            issue(kt + NS - 1, nx);
+            compute(st);
+            st = st + 1 == NS ? 0 : st + 1;
+            nx = nx + 1 == NS ? 0 : nx + 1;
         }
         wait_vm<0>();
     }
@@ -420,7 +414,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
 {
     if constexpr (PF == 6 || PF == 7) {
         static_assert(KFAST, "the DMA pipeline needs whole 16-byte chunks");
-        gemm_tile_dma<BM, BN, WM, WN, FA, FB, SP, PF == 6 ? 2 : 3, PF, SWAP>(p, tm, tn, split, smem);
+        gemm_tile_dma<BM, BN, WM, WN, FA, FB, SP, PF == 7 ? 3 : 2, PF, SWAP>(p, tm, tn, split, smem);
         return;
     }
     constexpr int NT = WM * WN * 64;
