@@ -112,6 +112,65 @@ def cpu_baseline(M, N, K, target_s=20.0):
             "sample": f"{done_rows} of {M} rows of the {M}x{N}x{K} GEMM (FP64, exact decode), {spent:.1f} s"}
 
 
+def bench_ace(lib, base, size=512, iters=100, counts=(1, 2, 4, 8)):
+    """Concurrent-stream study at size^3: `n` streams each run `iters`
+    back-to-back GEMMs (dense, 2:4 on A, or half of the streams each) from a
+    common start event.  Per stream: time from the start to its last GEMM.
+    Reported per (mode, n): makespan, aggregate dense-equivalent TFLOP/s,
+    speedup = n x (one-stream time) / makespan, overlap (share of the
+    makespan with at least two streams still running, i.e. the second-latest
+    stream end over the latest), the coefficient of variation of the stream
+    times and both fairness measures."""
+    import torch
+    from paper_2602_10262_amd import synth
+    M = N = K = size
+    xa = torch.from_numpy(synth.normal_outliers(7, (M, K))).cuda()
+    xb = torch.from_numpy(synth.normal_outliers(8, (N, K))).cuda()
+    qa, _, da = lib.fp8_quantize(xa, 0, lib.FP8_SCALE_ROW, stream=base)
+    qb, _, db = lib.fp8_quantize(xb, 0, lib.FP8_SCALE_ROW, stream=base)
+    va, ma, _ = lib.fp8_sparse24_prune_compress(qa, 0, with_mask=False, stream=base)
+    torch.cuda.synchronize()
+    flops = 2.0 * M * N * K
+    outs = [torch.empty((M, N), dtype=torch.bfloat16, device="cuda") for _ in range(max(counts))]
+    streams = [torch.cuda.Stream() for _ in range(max(counts))]
+
+    def run(n, mode):
+        start = torch.cuda.Event(enable_timing=True)
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+        start.record(base)
+        for i in range(n):
+            st = streams[i]
+            st.wait_event(start)
+            sparse = mode == "sparse" or (mode == "mixed" and i % 2 == 1)
+            with torch.cuda.stream(st):   # any temporary belongs to this stream
+                for _ in range(iters):
+                    if sparse:
+                        lib.fp8_sparse24_gemm(va, ma, qb, lib.FP8_SPARSE_A, da, db, c=outs[i], stream=st)
+                    else:
+                        lib.fp8_gemm(qa, qb, da, db, c=outs[i], stream=st)
+            ends[i].record(st)
+        torch.cuda.synchronize()
+        return [start.elapsed_time(e) for e in ends]
+
+    res = {"size": size, "iters_per_stream": iters, "modes": {}}
+    for mode in ("dense", "sparse", "mixed"):
+        run(1, mode)   # warm-up
+        one = run(1, mode)[0]
+        rows = []
+        for n in counts:
+            t = run(n, mode)
+            mk = max(t)
+            srt = sorted(t)
+            mean = sum(t) / n
+            sd = (sum((x - mean) ** 2 for x in t) / n) ** 0.5
+            rows.append({"streams": n, "makespan_ms": mk, "tflops": n * iters * flops / (mk * 1e-3) / 1e12,
+                         "speedup": n * one / mk, "overlap": (srt[-2] / mk) if n > 1 else 0.0,
+                         "cv": sd / mean, "fairness_range": 1.0 - (srt[-1] - srt[0]) / mean,
+                         "fairness_minmax": srt[0] / srt[-1]})
+        res["modes"][mode] = {"one_stream_ms": one, "rows": rows}
+    return res
+
+
 def bench_sparse(lib, qa, da, qb, db, iters, warmup, stream):
     import torch
     M, K = qa.shape
@@ -438,9 +497,26 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.quick:
+        # 256^3: uniform [-1, 1) inputs, per-tensor 448/amax scales, FP32 out
+        from paper_2602_10262_amd import synth
+        x1 = torch.from_numpy(synth.uniform(0, 0, (256, 256))).cuda()
+        y1 = torch.from_numpy(synth.uniform(0, 1, (256, 256))).cuda()
+        q1, _, d1 = lib.fp8_quantize(x1, 0, lib.FP8_SCALE_TENSOR, stream=stream)
+        r1, _, e1 = lib.fp8_quantize(y1, 0, lib.FP8_SCALE_TENSOR, stream=stream)
+        c1 = torch.empty((256, 256), dtype=torch.float32, device="cuda")
+        ms1 = time_events(lambda: lib.fp8_gemm(q1, r1, d1, e1, c=c1, stream=stream), 200, stream)
+        extra["gemm_256"] = {"us": ms1 * 1e3, "tflops": 2.0 * 256 ** 3 / (ms1 * 1e-3) / 1e12,
+                             "plan": list(lib.fp8_gemm_plan_resolve(lib.gemm_args(q1, r1, d1, e1, c1)))}
+        log(f"256^3 per-tensor FP32 out: {ms1 * 1e3:.2f} us per launch")
         log("grouped: 64 problems ...")
         extra["grouped"] = bench_grouped(lib, stream)
         log(f"grouped {extra['grouped']['grouped_tflops']:.0f} TF/s vs plain {extra['grouped']['plain_tflops']:.0f}")
+        torch.cuda.empty_cache()
+        log("concurrent streams (512^3) ...")
+        extra["ace"] = bench_ace(lib, stream)
+        for mode, r in extra["ace"]["modes"].items():
+            log(f"  {mode}: " + ", ".join(f"{x['streams']} streams {x['tflops']:.0f} TF/s x{x['speedup']:.2f}"
+                                          for x in r["rows"]))
         torch.cuda.empty_cache()
         log("served stream ...")
         extra["served"] = bench_served(lib, n_requests=args.requests)

@@ -69,19 +69,21 @@ __device__ __forceinline__ void static_for(F &&f)
     X(16, 128, 128, 2, 2, 1, 3)    \
     X(17, 256, 128, 2, 2, 1, 7)    \
     X(18, 128, 256, 2, 2, 1, 7)    \
-    X(19, 256, 256, 2, 4, 1, 6)
+    X(19, 256, 256, 2, 4, 1, 6)    \
+    X(20, 16, 256, 1, 4, 1, 8)     \
+    X(21, 32, 256, 1, 4, 1, 8)     \
+    X(22, 64, 256, 1, 4, 1, 7)
 
 
-// LDS of one tile: NSTAGE stages (2 for the register-prefetch loops and the
-// two-stage DMA loop, 3 for the loop that also prefetches fragments and for
-// the three-stage DMA loop).
+// LDS of one tile: NSTAGE stages (2 for the register-prefetch loops, 3 for
+// the loop that also prefetches fragments, PF - 4 for the DMA loops).
 template <int BM, int BN, bool SP, int PF = 2>
 struct TileSmem {
     static constexpr int A_BYTES = SP ? BM * 64 : BM * 128;
     static constexpr int M_BYTES = SP ? BM * 16 : 0;
     static constexpr int B_BYTES = BN * 128;
     static constexpr int STAGE = A_BYTES + M_BYTES + B_BYTES;
-    static constexpr int NSTAGE = (PF == 3 || PF == 7) ? 3 : 2;
+    static constexpr int NSTAGE = PF == 3 ? 3 : (PF >= 6 ? PF - 4 : 2);
     static constexpr int TOTAL = NSTAGE * STAGE;
 };
 
@@ -229,7 +231,7 @@ __device__ __forceinline__ void wait_vm()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// LDS-DMA pipeline (PF 6: NS = 2 LDS stages, PF 7: NS = 3).  Global tiles go
+// LDS-DMA pipeline (PF 6, 7, 8: NS = PF - 4 = 2, 3, 4 LDS stages).  Global tiles go
 // straight from memory into LDS without passing through registers, which
 // frees the staging registers for larger wave tiles (a 128 x 128 wave tile
 // reads half the LDS bytes per MFMA of a 64 x 64 one).  Each 1 KiB block of
@@ -254,7 +256,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     static_assert(NW % 2 == 0, "the per-lane swizzle must not change between rounds");
     constexpr int QA = S::A_BYTES / 1024, QM = S::M_BYTES / 1024, QB = S::B_BYTES / 1024;
     static_assert(S::A_BYTES % 1024 == 0 && S::M_BYTES % 1024 == 0 && S::B_BYTES % 1024 == 0, "1 KiB blocks");
-    static_assert(QA % NW == 0 && QB % NW == 0 && (QM % NW == 0 || QM < NW), "blocks per wave");
+    static_assert((QA % NW == 0 || QA < NW) && QB % NW == 0 && (QM % NW == 0 || QM < NW), "blocks per wave");
     constexpr int RA = QA / NW, RB = QB / NW, RM = QM / NW;   // rounds per wave per stage
     constexpr int PER = RA + RB + RM;                          // DMA instructions per wave per stage (at least)
     static_assert((NS - 2) * PER < 64, "vmcnt range");
@@ -300,11 +302,16 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
         // whole chunks past the end of K read as zero: point them past the range
         const int va = SP ? (k0 / 2 + ca * 16 < Kv ? voff_a : rec_a) : (k0 + ca * 16 < kend ? voff_a : rec_a);
         const int vb = k0 + cd * 16 < kend ? voff_b : rec_b;
-        static_for<0, RA>([&](auto uu) {
-            constexpr int u = decltype(uu)::value;
-            constexpr int rows = SP ? 16 : 8;
-            dma16(sb + (wave + u * NW) * 1024, va, rs_a, u * NW * rows * (int)p.lda + (SP ? k0 / 2 : k0));
-        });
+        if constexpr (RA > 0) {
+            static_for<0, RA>([&](auto uu) {
+                constexpr int u = decltype(uu)::value;
+                constexpr int rows = SP ? 16 : 8;
+                dma16(sb + (wave + u * NW) * 1024, va, rs_a, u * NW * rows * (int)p.lda + (SP ? k0 / 2 : k0));
+            });
+        } else {
+            // narrow tiles: fewer A blocks than waves
+            if (wave < QA) dma16(sb + wave * 1024, va, rs_a, SP ? k0 / 2 : k0);
+        }
         if constexpr (SP) {
             const int vm = k0 / 8 < Km ? voff_m : rec_m;
             if constexpr (RM > 0) {
@@ -401,8 +408,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
 // KFAST: K is a multiple of 16 (dense) or 128 (compressed operand), so every
 // 16-byte chunk is either wholly inside the operand or wholly outside.
 // PF: pipeline.  2: two register sets, global loads two steps ahead; 1: one
-// step ahead; 3: three LDS stages and fragments read one step ahead; 6 / 7:
-// global -> LDS DMA with two / three LDS stages (gemm_tile_dma).
+// step ahead; 3: three LDS stages and fragments read one step ahead; 6 / 7 /
+// 8: global -> LDS DMA with two / three / four LDS stages (gemm_tile_dma).
 // SWAP (dense only): run the MFMA with B rows in its A slot, so a lane ends
 // up with four consecutive j of one i (vector stores for a row-major output);
 // without it a lane holds four consecutive i of one j, which suits a
@@ -412,9 +419,16 @@ template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool KFAST = 
           bool SWAP = !SP>
 __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
 {
-    if constexpr (PF == 6 || PF == 7) {
+    if constexpr (PF >= 6) {
         static_assert(KFAST, "the DMA pipeline needs whole 16-byte chunks");
-        gemm_tile_dma<BM, BN, WM, WN, FA, FB, SP, PF == 7 ? 3 : 2, PF, SWAP>(p, tm, tn, split, smem);
+        if constexpr (SP && BM < 64) {
+            // the metadata of fewer than 64 rows does not fill a 1 KiB DMA
+            // block: such 2:4 tiles take the register pipeline (the LDS
+            // allocated for PF holds its two stages)
+            gemm_tile<BM, BN, WM, WN, FA, FB, SP, KFAST, 2, SWAP>(p, tm, tn, split, smem);
+        } else {
+            gemm_tile_dma<BM, BN, WM, WN, FA, FB, SP, PF - 4, PF, SWAP>(p, tm, tn, split, smem);
+        }
         return;
     }
     constexpr int NT = WM * WN * 64;
