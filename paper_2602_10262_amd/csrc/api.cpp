@@ -169,6 +169,8 @@ fp8_status resolve_plan(const Prepared &pr, const fp8_plan *plan, fp8_plan &res)
     if (plan) {
         if (plan->tile >= num_tiles()) return set_error(FP8_ERR_ARG, "plan.tile out of range");
         if (plan->tile >= 0) {
+            if (pr.sparse && !tile_desc(plan->tile).sparse_ok)
+                return set_error(FP8_ERR_ARG, "plan.tile has no 2:4 kernel");
             res.tile = plan->tile;
             const TileDesc &t = tile_desc(res.tile);
             res.split_k = default_splits(cdiv(pr.key.mk, t.bm) * cdiv(pr.key.nk, t.bn), pr.key.kk);

@@ -6,7 +6,7 @@
 
 namespace fp8k {
 
-#define FP8_DESC(i, bm, bn, wm, wn, occ, pf) {bm, bn, wm * wn, 1},
+#define FP8_DESC(i, bm, bn, wm, wn, occ, pf) {bm, bn, wm * wn, tile_sparse_ok(bm) ? 1 : 0},
 static const TileDesc kTiles[] = {FP8_TILE_LIST(FP8_DESC)};
 #undef FP8_DESC
 

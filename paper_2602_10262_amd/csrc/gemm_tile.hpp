@@ -72,8 +72,14 @@ __device__ __forceinline__ void static_for(F &&f)
     X(19, 256, 256, 2, 4, 1, 6)    \
     X(20, 16, 256, 1, 4, 1, 8)     \
     X(21, 32, 256, 1, 4, 1, 8)     \
-    X(22, 64, 256, 1, 4, 1, 7)
+    X(22, 64, 256, 1, 4, 1, 7)     \
+    X(23, 128, 256, 2, 4, 1, 7)
 
+
+// Whether a tile of BM rows has a 2:4 kernel: its compressed rows fill whole
+// 1 KiB DMA blocks of metadata (BM % 64 == 0), or fit the register pipeline's
+// single round of loads (BM <= 32).
+constexpr bool tile_sparse_ok(int bm) { return bm % 64 == 0 || bm <= 32; }
 
 // LDS of one tile: NSTAGE stages (2 for the register-prefetch loops, 3 for
 // the loop that also prefetches fragments, PF - 4 for the DMA loops).
@@ -256,8 +262,11 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     static_assert(NW % 2 == 0, "the per-lane swizzle must not change between rounds");
     constexpr int QA = S::A_BYTES / 1024, QM = S::M_BYTES / 1024, QB = S::B_BYTES / 1024;
     static_assert(S::A_BYTES % 1024 == 0 && S::M_BYTES % 1024 == 0 && S::B_BYTES % 1024 == 0, "1 KiB blocks");
-    static_assert((QA % NW == 0 || QA < NW) && QB % NW == 0 && (QM % NW == 0 || QM < NW), "blocks per wave");
-    constexpr int RA = QA / NW, RB = QB / NW, RM = QM / NW;   // rounds per wave per stage
+    static_assert(QM % NW == 0 || QM < NW, "metadata blocks per wave");
+    // full rounds per wave per stage; the first QA % NW (QB % NW) waves take
+    // one more A (B) block
+    constexpr int RA = QA / NW, RB = QB / NW, RM = QM / NW;
+    constexpr int XA = QA % NW, XB = QB % NW;
     constexpr int PER = RA + RB + RM;                          // DMA instructions per wave per stage (at least)
     static_assert((NS - 2) * PER < 64, "vmcnt range");
 
@@ -302,15 +311,14 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
         // whole chunks past the end of K read as zero: point them past the range
         const int va = SP ? (k0 / 2 + ca * 16 < Kv ? voff_a : rec_a) : (k0 + ca * 16 < kend ? voff_a : rec_a);
         const int vb = k0 + cd * 16 < kend ? voff_b : rec_b;
-        if constexpr (RA > 0) {
-            static_for<0, RA>([&](auto uu) {
-                constexpr int u = decltype(uu)::value;
-                constexpr int rows = SP ? 16 : 8;
-                dma16(sb + (wave + u * NW) * 1024, va, rs_a, u * NW * rows * (int)p.lda + (SP ? k0 / 2 : k0));
-            });
-        } else {
-            // narrow tiles: fewer A blocks than waves
-            if (wave < QA) dma16(sb + wave * 1024, va, rs_a, SP ? k0 / 2 : k0);
+        constexpr int rows_a_blk = SP ? 16 : 8;   // rows per 1 KiB block
+        static_for<0, RA>([&](auto uu) {
+            constexpr int u = decltype(uu)::value;
+            dma16(sb + (wave + u * NW) * 1024, va, rs_a, u * NW * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
+        });
+        if constexpr (XA > 0) {
+            if (wave < XA)
+                dma16(sb + (wave + RA * NW) * 1024, va, rs_a, RA * NW * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
         }
         if constexpr (SP) {
             const int vm = k0 / 8 < Km ? voff_m : rec_m;
@@ -327,6 +335,10 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
             constexpr int u = decltype(uu)::value;
             dma16(sb + S::A_BYTES + S::M_BYTES + (wave + u * NW) * 1024, vb, rs_b, u * NW * 8 * (int)p.ldb + k0);
         });
+        if constexpr (XB > 0) {
+            if (wave < XB)
+                dma16(sb + S::A_BYTES + S::M_BYTES + (wave + RB * NW) * 1024, vb, rs_b, RB * NW * 8 * (int)p.ldb + k0);
+        }
     };
 
     v4f acc[TM][TN];
@@ -421,10 +433,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
 {
     if constexpr (PF >= 6) {
         static_assert(KFAST, "the DMA pipeline needs whole 16-byte chunks");
-        if constexpr (SP && BM < 64) {
+        if constexpr (SP && BM % 64 != 0) {
             // the metadata of fewer than 64 rows does not fill a 1 KiB DMA
-            // block: such 2:4 tiles take the register pipeline (the LDS
-            // allocated for PF holds its two stages)
+            // block: such 2:4 tiles (BM <= 32) take the register pipeline
+            // (the LDS allocated for PF holds its two stages)
             gemm_tile<BM, BN, WM, WN, FA, FB, SP, KFAST, 2, SWAP>(p, tm, tn, split, smem);
         } else {
             gemm_tile_dma<BM, BN, WM, WN, FA, FB, SP, PF - 4, PF, SWAP>(p, tm, tn, split, smem);
@@ -440,7 +452,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
     constexpr int B_CH = BN * 8;
     constexpr int A_PER = (A_CH + NT - 1) / NT, B_PER = (B_CH + NT - 1) / NT;
     constexpr int M_PER = (M_CH + NT - 1) / NT;
-    static_assert((A_CH % NT == 0 || A_CH < NT) && (B_CH % NT == 0 || B_CH < NT), "tile/thread mismatch");
+    static_assert(PF >= 6 || ((A_CH % NT == 0 || A_CH < NT) && (B_CH % NT == 0 || B_CH < NT)),
+                  "tile/thread mismatch");
     static_assert(TM >= 1 && TN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
 
     const int tid = threadIdx.x;

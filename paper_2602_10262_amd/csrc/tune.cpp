@@ -64,6 +64,7 @@ static fp8_status tune_prepared(const Prepared &pr, int iters, hipStream_t st, f
     const int steps = (pr.p.K + kBKHost - 1) / kBKHost;
     for (int t = 0; t < num_tiles(); ++t) {
         const TileDesc &d = tile_desc(t);
+        if (pr.sparse && !d.sparse_ok) continue;
         const int64_t nb = ((pr.key.mk + d.bm - 1) / d.bm) * ((pr.key.nk + d.bn - 1) / d.bn);
         for (int s : {1, 2, 4, 8, 16, 32}) {
             if (s > steps) break;
@@ -191,6 +192,7 @@ fp8_status fp8_tune_cache_load(const char *path)
                         &mk, &nk, &kk, &fa, &fb, &ob, &si, &sj, &sp, &tile, &split, &us) != 12)
             continue;
         if (tile < 0 || tile >= num_tiles() || split < 1) continue;
+        if (sp && !tile_desc(tile).sparse_ok) continue;
         std::lock_guard<std::mutex> lk(g_mu);
         g_cache[KeyT{mk, nk, kk, fa, fb, ob, si, sj, sp}] = Entry{fp8_plan{tile, split}, us};
         ++n;

@@ -43,7 +43,7 @@ def test_dense_ragged_shapes(gpu, M, N, K, fa, bf16):
     check_gemm(c, qa, fa, qb, 0, da, db, bf16, f"{M}x{N}x{K}")
 
 
-NUM_TILES = 23   # tile configurations the library exports (checked on the host)
+NUM_TILES = 24   # tile configurations the library exports (checked on the host)
 
 
 @pytest.mark.parametrize("tile", list(range(NUM_TILES)))
@@ -137,6 +137,12 @@ def test_sparse_every_tile(gpu, tile):
     M, N, K = 150, 200, 512
     qa, da, qb, db = _sparse_case(M, N, K, 13)
     va, ma, _, pa = orc.prune24(qa, 0)
+    if not gpu.fp8_tile_info(tile)["sparse"]:
+        # dense-only tile: the plan is rejected before any launch
+        with pytest.raises(gpu.Fp8Error):
+            gpu.fp8_sparse24_gemm(dev(va), dev(ma), codes_with_pad(N, K, qb), gpu.FP8_SPARSE_A, dev(da), dev(db),
+                                  plan=(tile, 2))
+        return
     c = gpu.fp8_sparse24_gemm(dev(va), dev(ma), codes_with_pad(N, K, qb), gpu.FP8_SPARSE_A, dev(da), dev(db),
                               plan=(tile, 2))
     torch.cuda.synchronize()
