@@ -148,6 +148,9 @@ fp8_plan heuristic_plan(const GemmKey &k)
     const int64_t M = k.mk, N = k.nk;
     if (N <= 16) p.tile = 8;
     else if (N <= 32) p.tile = 9;
+    // single-wave 16 x 32 tiles on a 12-stage DMA ring: enough workgroups
+    // without split-K once N is large
+    else if (!k.sparse && M <= 16 && N >= 4096 && (k.kk % 16) == 0) p.tile = 24;
     else if (M <= 16) p.tile = 4;
     else if (M <= 32) p.tile = 5;
     else if (M <= 64) p.tile = 7;

@@ -73,7 +73,8 @@ __device__ __forceinline__ void static_for(F &&f)
     X(20, 16, 256, 1, 4, 1, 8)     \
     X(21, 32, 256, 1, 4, 1, 8)     \
     X(22, 64, 256, 1, 4, 1, 7)     \
-    X(23, 128, 256, 2, 4, 1, 7)
+    X(23, 128, 256, 2, 4, 1, 7)    \
+    X(24, 16, 32, 1, 1, 2, 16)
 
 
 // Whether a tile of BM rows has a 2:4 kernel: its compressed rows fill whole
@@ -229,6 +230,18 @@ __device__ __forceinline__ void dma16(uint32_t lds, int voff, __amdgpu_buffer_rs
                  : "memory");
 }
 
+// A buffer resource whose pieces are wave-uniform by construction (the tile
+// base and its byte range); readfirstlane makes that explicit, so the
+// resource lives in scalar registers as the DMA instruction requires.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const uint8_t *base, int records)
+{
+    const uint64_t b = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    void *u = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(u, (short)0, __builtin_amdgcn_readfirstlane(records), kBufferFlags);
+}
+
 // s_waitcnt vmcnt(N) with the other counters left alone (gfx9 encoding).
 template <int N>
 __device__ __forceinline__ void wait_vm()
@@ -237,7 +250,7 @@ __device__ __forceinline__ void wait_vm()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// LDS-DMA pipeline (PF 6, 7, 8: NS = PF - 4 = 2, 3, 4 LDS stages).  Global tiles go
+// LDS-DMA pipeline (PF >= 6: NS = PF - 4 LDS stages).  Global tiles go
 // straight from memory into LDS without passing through registers, which
 // frees the staging registers for larger wave tiles (a 128 x 128 wave tile
 // reads half the LDS bytes per MFMA of a 64 x 64 one).  Each 1 KiB block of
@@ -259,7 +272,6 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     constexpr int TM = WTM / 16, TN = WTN / 16;
     using S = TileSmem<BM, BN, SP, PF>;
     static_assert(S::NSTAGE == NS, "stage count");
-    static_assert(NW % 2 == 0, "the per-lane swizzle must not change between rounds");
     constexpr int QA = S::A_BYTES / 1024, QM = S::M_BYTES / 1024, QB = S::B_BYTES / 1024;
     static_assert(S::A_BYTES % 1024 == 0 && S::M_BYTES % 1024 == 0 && S::B_BYTES % 1024 == 0, "1 KiB blocks");
     static_assert(QM % NW == 0 || QM < NW, "metadata blocks per wave");
@@ -283,17 +295,15 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
 
     const int rows_a = min(BM, p.M - m0), rows_b = min(BN, p.N - n0);
     const int rec_a = rows_a * (int)p.lda, rec_b = rows_b * (int)p.ldb, rec_m = SP ? rows_a * (int)p.ldm : 0;
-    const __amdgpu_buffer_rsrc_t rs_a =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(p.a + (int64_t)m0 * p.lda), (short)0, rec_a, kBufferFlags);
-    const __amdgpu_buffer_rsrc_t rs_b =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(p.b + (int64_t)n0 * p.ldb), (short)0, rec_b, kBufferFlags);
-    const __amdgpu_buffer_rsrc_t rs_m = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(SP ? p.meta + (int64_t)m0 * p.ldm : p.a), (short)0, rec_m, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rs_a = uniform_rsrc(p.a + (int64_t)m0 * p.lda, rec_a);
+    const __amdgpu_buffer_rsrc_t rs_b = uniform_rsrc(p.b + (int64_t)n0 * p.ldb, rec_b);
+    const __amdgpu_buffer_rsrc_t rs_m = uniform_rsrc(SP ? p.meta + (int64_t)m0 * p.ldm : p.a, rec_m);
 
     // Per-lane source of the first block a wave fills; later rounds move
-    // down by NW blocks (a whole number of rows, same swizzle phase).
-    // Dense rows (128 bytes): block q holds rows 8q .. 8q+7, lane l row
-    // 8q + l/8, slot l%8, so the source chunk is (l%8) ^ (l/8) ^ (q&1).
+    // down by NW blocks (a whole number of rows).  Dense rows (128 bytes):
+    // block q holds rows 8q .. 8q+7, lane l row 8q + l/8, slot l%8, so the
+    // source chunk is (l%8) ^ (l/8) ^ (q&1); round u of an odd number of
+    // waves flips the last term, so a second offset serves those rounds.
     const int cd = (lane & 7) ^ (lane >> 3) ^ (wave & 1);
     const int voff_b = (wave * 8 + (lane >> 3)) * (int)p.ldb + cd * 16;
     // A: dense as B; compressed values (64 bytes): block q holds rows 16q ..
@@ -311,14 +321,20 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
         // whole chunks past the end of K read as zero: point them past the range
         const int va = SP ? (k0 / 2 + ca * 16 < Kv ? voff_a : rec_a) : (k0 + ca * 16 < kend ? voff_a : rec_a);
         const int vb = k0 + cd * 16 < kend ? voff_b : rec_b;
+        // rounds whose block parity differs from the first one's (odd NW)
+        const int cdf = cd ^ 1;
+        const int vaf = SP ? va : (k0 + cdf * 16 < kend ? voff_a + (cdf - cd) * 16 : rec_a);
+        const int vbf = k0 + cdf * 16 < kend ? voff_b + (cdf - cd) * 16 : rec_b;
         constexpr int rows_a_blk = SP ? 16 : 8;   // rows per 1 KiB block
         static_for<0, RA>([&](auto uu) {
             constexpr int u = decltype(uu)::value;
-            dma16(sb + (wave + u * NW) * 1024, va, rs_a, u * NW * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
+            dma16(sb + (wave + u * NW) * 1024, ((u * NW) & 1) ? vaf : va, rs_a,
+                  u * NW * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
         });
         if constexpr (XA > 0) {
             if (wave < XA)
-                dma16(sb + (wave + RA * NW) * 1024, va, rs_a, RA * NW * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
+                dma16(sb + (wave + RA * NW) * 1024, ((RA * NW) & 1) ? vaf : va, rs_a,
+                      RA * NW * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
         }
         if constexpr (SP) {
             const int vm = k0 / 8 < Km ? voff_m : rec_m;
@@ -333,11 +349,13 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
         }
         static_for<0, RB>([&](auto uu) {
             constexpr int u = decltype(uu)::value;
-            dma16(sb + S::A_BYTES + S::M_BYTES + (wave + u * NW) * 1024, vb, rs_b, u * NW * 8 * (int)p.ldb + k0);
+            dma16(sb + S::A_BYTES + S::M_BYTES + (wave + u * NW) * 1024, ((u * NW) & 1) ? vbf : vb, rs_b,
+                  u * NW * 8 * (int)p.ldb + k0);
         });
         if constexpr (XB > 0) {
             if (wave < XB)
-                dma16(sb + S::A_BYTES + S::M_BYTES + (wave + RB * NW) * 1024, vb, rs_b, RB * NW * 8 * (int)p.ldb + k0);
+                dma16(sb + S::A_BYTES + S::M_BYTES + (wave + RB * NW) * 1024, ((RB * NW) & 1) ? vbf : vb, rs_b,
+                      RB * NW * 8 * (int)p.ldb + k0);
         }
     };
 
@@ -420,8 +438,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
 // KFAST: K is a multiple of 16 (dense) or 128 (compressed operand), so every
 // 16-byte chunk is either wholly inside the operand or wholly outside.
 // PF: pipeline.  2: two register sets, global loads two steps ahead; 1: one
-// step ahead; 3: three LDS stages and fragments read one step ahead; 6 / 7 /
-// 8: global -> LDS DMA with two / three / four LDS stages (gemm_tile_dma).
+// step ahead; 3: three LDS stages and fragments read one step ahead; 6 and
+// up: global -> LDS DMA with PF - 4 LDS stages (gemm_tile_dma).
 // SWAP (dense only): run the MFMA with B rows in its A slot, so a lane ends
 // up with four consecutive j of one i (vector stores for a row-major output);
 // without it a lane holds four consecutive i of one j, which suits a
