@@ -449,7 +449,8 @@ def main():
                     help="only launch the headline GEMM 3 times and a 1 GiB device copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the GEMM would shard by "
+              "columns of B with no exchange; that is not built)",
               file=sys.stderr)
         sys.exit(2)
 

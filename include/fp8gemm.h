@@ -109,8 +109,9 @@ typedef struct {
     int split_k;
 } fp8_plan;
 
-/* Describes compiled tile `tile`: macro-tile rows/cols and whether it is a
- * sparse-capable kernel.  Returns FP8_ERR_ARG past the last tile. */
+/* Describes compiled tile `tile`: macro-tile rows/cols, waves per workgroup
+ * and whether it has a 2:4 kernel (*sparse = 0: a 2:4 plan naming it is
+ * rejected with FP8_ERR_ARG).  Returns FP8_ERR_ARG past the last tile. */
 fp8_status fp8_tile_info(int tile, int *block_m, int *block_n, int *waves, int *sparse);
 int fp8_num_tiles(void);
 
