@@ -225,7 +225,7 @@ def bench_sparse(lib, qa, da, qb, db, iters, warmup, stream):
 
 
 def bench_shape(lib, M, N, K, fa, stream, iters=20, tune=True, rotate=1, sparse_too=True):
-    """One configured shape: tuned dense and 2:4 (on the identical pruned A)
+    """One shape of the sweep: tuned dense and 2:4 (on the identical pruned A)
     timings; B rotated over `rotate` copies so large caches cannot hold it."""
     import torch
     from paper_2602_10262_amd import synth

@@ -39,7 +39,7 @@ typedef enum {
     FP8_ERR_ARG = 1,          /* null or inconsistent argument, workspace too small */
     FP8_ERR_SHAPE = 2,        /* a dimension out of range */
     FP8_ERR_ALIGN = 3,        /* pointer or leading dimension not 16-byte aligned */
-    FP8_ERR_UNSUPPORTED = 4,  /* valid request this build has no kernel for */
+    FP8_ERR_UNSUPPORTED = 4,  /* valid request the library has no kernel for */
     FP8_ERR_HIP = 5,          /* a HIP runtime call failed (text in fp8_last_error) */
     FP8_ERR_NOMEM = 6,        /* a library-owned allocation failed */
     FP8_ERR_BUDGET = 7,       /* server: request larger than the whole HBM budget */

@@ -21,11 +21,11 @@ def _run_dense(gpu, qa, qb, da, db, fa, fb, bf16, plan=None):
     return c
 
 
-def test_config1_256_cube_per_tensor_fp32(gpu):
+def test_256_cube_uniform_per_tensor_fp32(gpu):
     """M = N = K = 256, uniform[-1, 1) inputs, per-tensor 448/amax scales,
     E4M3 x E4M3, FP32 output."""
     qa, da, qb, db = operands(256, 256, 256, 0, "uniform", 0, 0, False)
-    log("config 1: 256^3 E4M3 per-tensor FP32")
+    log("256^3 E4M3 uniform inputs, per-tensor scales, FP32 out")
     c = _run_dense(gpu, qa, qb, da, db, 0, 0, False)
     check_gemm(c, qa, 0, qb, 0, da, db, False, "256^3")
 

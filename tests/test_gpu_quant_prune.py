@@ -101,7 +101,7 @@ def test_prune_bit_exact(gpu, fmt, rows, K, kind):
 
 
 def test_prune_full_size_bit_exact(gpu):
-    """A 16384 x 16384 E4M3 matrix (the largest configured A): prune on the
+    """A 16384 x 16384 E4M3 matrix (the largest A of the square sweep): prune on the
     GPU, compare sampled rows with the oracle and check the invariants on all."""
     import torch
     rows = K = 16384
