@@ -56,6 +56,19 @@ def test_every_tile_and_split(gpu, tile, split):
     check_gemm(c, qa, 0, qb, 0, da, db, False, f"tile {tile} split {split}")
 
 
+@pytest.mark.parametrize("tile", list(range(NUM_TILES)))
+@pytest.mark.parametrize("split", [1, 2])
+def test_every_tile_partial_last_k_step(gpu, tile, split):
+    """K a multiple of 16 but not of 128: the last K step of the last split is
+    partial, so its chunks past K must read as zero (the DMA tiles fetch them
+    from past the buffer range; the register tiles select zero)."""
+    M, N, K = 70, 90, 656
+    qa, da, qb, db = operands(M, N, K, 21, "normal", 0, 0, True)
+    log(f"tile={tile} split={split} K={K}")
+    c = _run_dense(gpu, qa, qb, da, db, 0, 0, False, plan=(tile, split))
+    check_gemm(c, qa, 0, qb, 0, da, db, False, f"tile {tile} split {split} K {K}")
+
+
 def test_both_e5m2_operands(gpu):
     qa, da, qb, db = operands(96, 80, 512, 3, "normal", 1, 1, True)
     c = _run_dense(gpu, qa, qb, da, db, 1, 1, True)
