@@ -343,7 +343,7 @@ def bench_grouped(lib, stream, seed=0, count=64):
     res["plain_ms"] = plain_ms
     res["plain_tflops"] = flops / plain_ms / 1e9
     best = None
-    for tile in (9, 12, 13, 0, 7):
+    for tile in (9, 12, 13, 0, 7, 17, 19, 23):
         plan = lib.GroupedPlan(probs, tile=tile, use_graph=True)
         plan.run(stream)
         ms = time_events(lambda: plan.run(stream), 5, stream)

@@ -49,7 +49,7 @@ SPECS = [(1, 256, 512, False), (37, 384, 256, True), (200, 256, 1024, False), (5
          (300, 128, 384, True), (64, 640, 256, False), (17, 256, 768, False), (129, 256, 512, True)]
 
 
-@pytest.mark.parametrize("tile", [0, 3, 7, 8, 9, 12, 13])
+@pytest.mark.parametrize("tile", [0, 3, 7, 8, 9, 12, 13, 17, 19, 23])
 def test_grouped_matches_oracle(gpu, tile):
     import torch
     probs = _mix(1, SPECS)
