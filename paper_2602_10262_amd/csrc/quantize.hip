@@ -5,8 +5,9 @@
 // global atomic max per workgroup on the FP32 bit pattern, which orders
 // non-negative floats and puts NaN above infinity), then the encode pass that
 // rebuilds s, d from the amax word in every thread.
-// Per row: one workgroup per row does both passes; the second pass re-reads
-// the row, which is then resident in L2.
+// Per row: one workgroup per row does both passes; rows of up to 16384 codes
+// (a multiple of 16) stay in registers between them, longer ones are read
+// again (then resident in L2).
 // Every thread handles 16 consecutive elements of a row: four 128-bit loads,
 // one 128-bit store of 16 codes; a ragged row end is done element by element.
 #include "common.hpp"
@@ -135,6 +136,78 @@ __global__ void __launch_bounds__(kQThreads) quantize_rows(const float *x, int64
         chunk_encode<FMT>(row, cols, c0, s, q + r * ldq);
 }
 
+// Per row, one read: rows of up to R * 4096 codes (cols % 16 == 0) are held in
+// registers (R chunks of 16 per thread, all loads issued up front), so the
+// encode pass does not read the row again.  Same amax, scale and codes as
+// quantize_rows.
+template <int FMT, int R>
+__global__ void __launch_bounds__(kQThreads) quantize_rows_reg(const float *x, int64_t cols, int64_t ldx,
+                                                               uint8_t *q, int64_t ldq, float *s_out,
+                                                               float *d_out)
+{
+    __shared__ uint32_t red[kQThreads / 64];
+    const int64_t r = blockIdx.x;
+    const float *row = x + r * ldx;
+    float4 v[R][4];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int64_t c0 = ((int64_t)threadIdx.x + k * kQThreads) * 16;
+        if (c0 < cols) {
+            const float4 *p = reinterpret_cast<const float4 *>(row + c0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[k][t] = p[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[k][t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            uint32_t a = absbits(v[k][t].x), b = absbits(v[k][t].y), c = absbits(v[k][t].z), d = absbits(v[k][t].w);
+            a = a > b ? a : b;
+            c = c > d ? c : d;
+            a = a > c ? a : c;
+            m = m > a ? m : a;
+        }
+    m = block_max(m, red);
+    float s, d;
+    scale_from_amax<FMT>(__uint_as_float(m), s, d);
+    if (threadIdx.x == 0) {
+        s_out[r] = s;
+        d_out[r] = d;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int64_t c0 = ((int64_t)threadIdx.x + k * kQThreads) * 16;
+        if (c0 < cols) {
+            uint32_t w[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                w[t] = encode_fp8<FMT>(v[k][t].x * s) | (encode_fp8<FMT>(v[k][t].y * s) << 8) |
+                       (encode_fp8<FMT>(v[k][t].z * s) << 16) | (encode_fp8<FMT>(v[k][t].w * s) << 24);
+            *reinterpret_cast<uint4 *>(q + r * ldq + c0) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+template <int FMT>
+static void launch_rows(const float *x, int64_t rows, int64_t cols, int64_t ldx, uint8_t *q, int64_t ldq,
+                        float *s, float *d, hipStream_t st)
+{
+    const dim3 g((unsigned)rows);
+    if (cols % 16 == 0 && cols <= 4096)
+        quantize_rows_reg<FMT, 1><<<g, kQThreads, 0, st>>>(x, cols, ldx, q, ldq, s, d);
+    else if (cols % 16 == 0 && cols <= 8192)
+        quantize_rows_reg<FMT, 2><<<g, kQThreads, 0, st>>>(x, cols, ldx, q, ldq, s, d);
+    else if (cols % 16 == 0 && cols <= 16384)
+        quantize_rows_reg<FMT, 4><<<g, kQThreads, 0, st>>>(x, cols, ldx, q, ldq, s, d);
+    else
+        quantize_rows<FMT><<<g, kQThreads, 0, st>>>(x, rows, cols, ldx, q, ldq, s, d);
+}
+
 // Exhaustive encoder check support: codes of the FP32 bit patterns lo .. lo+n-1.
 template <int FMT>
 __global__ void encode_bits(uint32_t lo, int64_t n, uint8_t *out)
@@ -155,10 +228,8 @@ hipError_t launch_quantize(const float *x, int64_t rows, int64_t cols, int64_t l
                            uint8_t *q, int64_t ldq, float *s, float *d, void *ws, hipStream_t st)
 {
     if (per_row) {
-        if (fmt == kE4M3)
-            quantize_rows<kE4M3><<<dim3((unsigned)rows), kQThreads, 0, st>>>(x, rows, cols, ldx, q, ldq, s, d);
-        else
-            quantize_rows<kE5M2><<<dim3((unsigned)rows), kQThreads, 0, st>>>(x, rows, cols, ldx, q, ldq, s, d);
+        if (fmt == kE4M3) launch_rows<kE4M3>(x, rows, cols, ldx, q, ldq, s, d, st);
+        else launch_rows<kE5M2>(x, rows, cols, ldx, q, ldq, s, d, st);
         return hipGetLastError();
     }
     uint32_t *amax = static_cast<uint32_t *>(ws);

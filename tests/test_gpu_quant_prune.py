@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("fmt", [0, 1])
 @pytest.mark.parametrize("per_row", [False, True])
 @pytest.mark.parametrize("shape,dist", [((256, 256), "uniform"), ((37, 53), "normal"), ((1, 16), "normal"),
-                                        ((300, 1000), "normal"), ((5, 4096), "uniform")])
+                                        ((300, 1000), "normal"), ((5, 4096), "uniform"), ((3, 8192), "normal"),
+                                        ((2, 12288), "normal"), ((2, 16384), "uniform"), ((2, 16400), "normal")])
 def test_quantize_bit_exact(gpu, fmt, per_row, shape, dist):
     import torch
     rows, cols = shape
