@@ -1,6 +1,7 @@
 // 2:4 prune + compress and decompress on gfx950: integer-only streaming passes.
 //
-// One thread per 32 consecutive codes of a row (eight groups of four): two
+// One thread per 32 consecutive codes of a row (eight groups of four; two
+// such chunks per thread on the row-per-block path when K % 32 == 0): two
 // 128-bit loads in, one 128-bit store of the 16 survivors, one 32-bit word of
 // metadata (eight nibbles, group 8w+n in bits 4n..4n+3) and one 32-bit word of
 // keep-mask out.  Survivor choice per group compares the 7-bit magnitude
@@ -91,6 +92,47 @@ __global__ void __launch_bounds__(kPThreads) prune24_kernel(const uint8_t *x, in
     }
 }
 
+// Rows of K % 32 == 0 codes, one row per blockIdx.y: thread t of block b takes
+// chunks (b * 2 * kPThreads + t) and that + kPThreads of its row (no index
+// division; both chunks' loads are issued before any group is pruned).
+// Same survivors, metadata and mask as prune24_kernel.
+__global__ void __launch_bounds__(kPThreads) prune24_rows_kernel(const uint8_t *x, int64_t K, int64_t ldx,
+                                                                 uint8_t *values, uint8_t *meta, uint8_t *mask)
+{
+    const int64_t r = blockIdx.y;
+    const int64_t cpr = K / 32;
+    const int64_t c0 = (int64_t)blockIdx.x * (2 * kPThreads) + threadIdx.x;
+    uint4 in[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t ch = c0 + h * kPThreads;
+        if (ch < cpr) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(x + r * ldx + ch * 32);
+            in[h][0] = src[0];
+            in[h][1] = src[1];
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t ch = c0 + h * kPThreads;
+        if (ch >= cpr) continue;
+        const uint32_t w[8] = {in[h][0].x, in[h][0].y, in[h][0].z, in[h][0].w,
+                               in[h][1].x, in[h][1].y, in[h][1].z, in[h][1].w};
+        uint32_t metaw = 0, maskw = 0, v[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            uint32_t vals, keep4;
+            const uint32_t nib = prune_group(w[g], vals, keep4);
+            metaw |= nib << (4 * g);
+            maskw |= keep4 << (4 * g);
+            v[g / 2] |= vals << (16 * (g % 2));
+        }
+        *reinterpret_cast<uint4 *>(values + r * (K / 2) + ch * 16) = make_uint4(v[0], v[1], v[2], v[3]);
+        *reinterpret_cast<uint32_t *>(meta + r * (K / 8) + ch * 4) = metaw;
+        if (mask) *reinterpret_cast<uint32_t *>(mask + r * (K / 8) + ch * 4) = maskw;
+    }
+}
+
 __global__ void __launch_bounds__(kPThreads) decompress24_kernel(const uint8_t *values, const uint8_t *meta,
                                                                  int64_t rows, int64_t K, uint8_t *out,
                                                                  int64_t ldo)
@@ -133,7 +175,13 @@ static int grid_for(int64_t items)
 hipError_t launch_prune24(const uint8_t *x, int64_t rows, int64_t K, int64_t ldx, uint8_t *values,
                           uint8_t *meta, uint8_t *mask, hipStream_t st)
 {
-    prune24_kernel<<<grid_for(rows * ((K + 31) / 32)), kPThreads, 0, st>>>(x, rows, K, ldx, values, meta, mask);
+    if (K % 32 == 0 && rows <= 65535) {
+        const int64_t cpr = K / 32;
+        const dim3 g((unsigned)((cpr + 2 * kPThreads - 1) / (2 * kPThreads)), (unsigned)rows);
+        prune24_rows_kernel<<<g, kPThreads, 0, st>>>(x, K, ldx, values, meta, mask);
+    } else {
+        prune24_kernel<<<grid_for(rows * ((K + 31) / 32)), kPThreads, 0, st>>>(x, rows, K, ldx, values, meta, mask);
+    }
     return hipGetLastError();
 }
 
