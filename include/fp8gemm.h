@@ -225,7 +225,16 @@ fp8_status fp8_grouped_plan_destroy(fp8_grouped_plan *plan);
  * up.  The result of a request does not depend on what else is in flight.
  * Latency = completion - arrival, where arrival is the request's
  * arrival_time_s on the server clock (seconds since fp8_server_create) or,
- * when negative, the time of the submit call. */
+ * when negative, the time of the submit call.
+ * Ordering: the server runs on streams of its own that are not ordered
+ * against the caller's streams, so x must hold its final values and c must
+ * not be written by other pending work when fp8_server_submit is called
+ * (synchronise the producing stream first); c is complete once wait/poll
+ * report FP8_OK.
+ * Failures: a request whose arguments the GEMM rejects fails with that
+ * status before anything is enqueued; if a launch fails after part of the
+ * request was enqueued, the ticket reports the failure only once that work
+ * has finished, and its memory is reused only then. */
 typedef struct {
     size_t hbm_budget_bytes;
     int num_streams;          /* 1 .. 16 */
@@ -262,8 +271,10 @@ fp8_status fp8_server_create(const fp8_server_config *cfg, fp8_server **srv);
  * may carry NULL device pointers.  Workspace needs are not modelled. */
 fp8_status fp8_server_create_simulated(const fp8_server_config *cfg, double gflop_per_ms, double launch_us,
                                        fp8_server **srv);
-/* Registers a weight: dense (meta NULL: w is N x K codes) or 2:4 (w = values
- * N x K/2, meta N x K/8).  w_descale: N floats.  Buffers stay caller-owned. */
+/* Registers a weight: dense (meta NULL: w is N x K codes, K % 16 == 0) or 2:4
+ * (w = values N x K/2, meta N x K/8, K % 8 == 0).  w_descale: N floats.
+ * w and meta must be 16-byte aligned (FP8_ERR_ALIGN), shapes as stated
+ * (FP8_ERR_SHAPE).  Buffers stay caller-owned. */
 fp8_status fp8_server_register_weight(fp8_server *srv, const uint8_t *w, const uint8_t *meta,
                                       const float *w_descale, int64_t N, int64_t K, fp8_fmt fmt,
                                       int *weight_id);

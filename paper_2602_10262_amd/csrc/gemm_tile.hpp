@@ -207,6 +207,152 @@ __device__ __forceinline__ void store4(const GemmParams &p, int i, int j, int sp
     }
 }
 
+// The staged store of write_tile for one output orientation: TR = the
+// result is stored transposed (output rows are j).  Pass t covers the
+// sixteen output rows of MFMA block t along the output-row index.  The
+// descales a lane needs are loaded once, before the workgroup barrier, so
+// their latency overlaps it: the row descales of every pass, and the column
+// descales of the one 16-byte column chunk the lane stores in every row.
+template <int BM, int BN, int WM, int WN, bool ALONG_J, int LDS_BYTES, bool TR>
+__device__ __forceinline__ void write_tile_staged(const GemmParams &p, const v4f (&acc)[BM / WM / 16][BN / WN / 16],
+                                                  int m0, int n0, int wave, int lane, uint8_t *smem)
+{
+    constexpr int NW = WM * WN;
+    constexpr int WTM = BM / WM, WTN = BN / WN;
+    constexpr int TM = WTM / 16, TN = WTN / 16;
+    constexpr int STRIDE = (WTN > WTM ? WTN : WTM) * 4 + 16;   // padded FP32 staging row (bytes)
+    static_assert(NW * 16 * STRIDE <= LDS_BYTES, "epilogue staging exceeds the tile's LDS");
+    constexpr int NPASS = TR ? TN : TM;
+    constexpr int OC = TR ? WTM : WTN;                          // output columns of this wave
+    constexpr bool ROW_PER_Q = TR ? ALONG_J : !ALONG_J;         // the four values sit in four output rows
+    constexpr int RQ = ROW_PER_Q ? 4 : 1;
+    const int wm = wave / WN, wn = wave % WN;
+    const int lr = lane & 15, lg = lane >> 4;
+    const bool bf = p.out_bf16 != 0;
+    const int esz = bf ? 2 : 4;
+    const int per = bf ? 8 : 4;                                 // output elements per 16-byte chunk
+    const int chunks_row = OC / per;                            // divides 64: a lane's chunk column is fixed
+    uint8_t *reg = smem + wave * 16 * STRIDE;
+    const int rows_out = TR ? p.N : p.M, cols_out = TR ? p.M : p.N;
+    const int orow0 = TR ? n0 + wn * WTN : m0 + wm * WTM;       // wave's first output row
+    const int ocol0 = TR ? m0 + wm * WTM : n0 + wn * WTN;       // wave's first output column
+    const float *rdesc = TR ? p.sj : p.si, *cdesc = TR ? p.si : p.sj;
+    const int rper = TR ? p.sj_per : p.si_per, cper = TR ? p.si_per : p.sj_per;
+    const bool vec_ok = ((p.ldc * esz) % 16) == 0 && ((reinterpret_cast<uintptr_t>(p.c) & 15) == 0);
+    const int cc = lane % chunks_row, rsub = lane / chunks_row, rstep = 64 / chunks_row;
+    const int ocol = ocol0 + cc * per;
+    float rd[NPASS][RQ], cd[8];
+    static_for<0, NPASS>([&](auto tt) {
+        constexpr int t = decltype(tt)::value;
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            const int orow = min(orow0 + t * 16 + (ROW_PER_Q ? 4 * lg + q : lr), rows_out - 1);
+            rd[t][q] = rdesc[rper ? orow : 0];
+        }
+    });
+#pragma unroll
+    for (int e = 0; e < 8; ++e) cd[e] = cdesc[cper ? min(ocol + e, cols_out - 1) : 0];
+    __syncthreads();   // every wave is done with the main loop's LDS
+    static_for<0, NPASS>([&](auto tt) {
+        constexpr int t = decltype(tt)::value;
+        // stage the pass's accumulators times their output row's descale
+        if constexpr (!TR) {
+            static_for<0, TN>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                const v4f &v = acc[t][j];
+                if constexpr (ALONG_J) {
+                    *reinterpret_cast<float4 *>(reg + lr * STRIDE + (j * 16 + 4 * lg) * 4) =
+                        make_float4(v[0] * rd[t][0], v[1] * rd[t][0], v[2] * rd[t][0], v[3] * rd[t][0]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        *reinterpret_cast<float *>(reg + (4 * lg + q) * STRIDE + (j * 16 + lr) * 4) = v[q] * rd[t][q];
+                }
+            });
+        } else {
+            static_for<0, TM>([&](auto ii) {
+                constexpr int i = decltype(ii)::value;
+                const v4f &v = acc[i][t];
+                if constexpr (!ALONG_J) {
+                    // four consecutive i of one j: four consecutive output columns
+                    *reinterpret_cast<float4 *>(reg + lr * STRIDE + (i * 16 + 4 * lg) * 4) =
+                        make_float4(v[0] * rd[t][0], v[1] * rd[t][0], v[2] * rd[t][0], v[3] * rd[t][0]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        *reinterpret_cast<float *>(reg + (4 * lg + q) * STRIDE + (i * 16 + lr) * 4) = v[q] * rd[t][q];
+                }
+            });
+        }
+        __syncthreads();
+        // store 16-byte chunks of whole output rows, times the column descale
+        for (int r = rsub; r < 16; r += rstep) {
+            const int orow = orow0 + t * 16 + r;
+            if (orow >= rows_out) break;
+            const float *src = reinterpret_cast<const float *>(reg + r * STRIDE + cc * per * 4);
+            float v[8];
+            const float4 x0 = *reinterpret_cast<const float4 *>(src);
+            v[0] = x0.x * cd[0]; v[1] = x0.y * cd[1]; v[2] = x0.z * cd[2]; v[3] = x0.w * cd[3];
+            uint8_t *dst = reinterpret_cast<uint8_t *>(p.c) + ((int64_t)orow * p.ldc + ocol) * esz;
+            const bool full = vec_ok && ocol + per <= cols_out;
+            if (bf) {
+                const float4 x1 = *reinterpret_cast<const float4 *>(src + 4);
+                v[4] = x1.x * cd[4]; v[5] = x1.y * cd[5]; v[6] = x1.z * cd[6]; v[7] = x1.w * cd[7];
+                uint16_t h[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) h[e] = f32_to_bf16_rne(v[e]);
+                if (full) {
+                    *reinterpret_cast<uint4 *>(dst) = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16,
+                                                                 h[4] | (uint32_t)h[5] << 16, h[6] | (uint32_t)h[7] << 16);
+                } else {
+                    for (int e = 0; e < 8 && ocol + e < cols_out; ++e) reinterpret_cast<uint16_t *>(dst)[e] = h[e];
+                }
+            } else {
+                if (full) *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                else
+                    for (int e = 0; e < 4 && ocol + e < cols_out; ++e) reinterpret_cast<float *>(dst)[e] = v[e];
+            }
+        }
+        __syncthreads();
+    });
+}
+
+// Epilogue of a workgroup tile: every wave writes its accumulators to C.
+// The output is staged through the wave's own region of LDS, sixteen output
+// rows at a time, so that global stores are 16-byte chunks of whole rows
+// (a wave writes 64 to 512 contiguous bytes of each row) instead of the
+// 8-byte pieces of sixteen rows that one MFMA result holds.  The value is
+// (acc * d_i) * d_j (transposed output: (acc * d_j) * d_i) in FP32: the
+// staged value carries the output row's descale, the column's is applied
+// when the row chunk is stored, as FP32 or as BF16 (RNE).  Split-K partial
+// sums go to the workspace through store4 instead.  Every wave of the
+// workgroup must call it (it synchronises the workgroup) once the main loop
+// no longer touches LDS.  LDS_BYTES: LDS the tile owns.
+template <int BM, int BN, int WM, int WN, bool ALONG_J, int LDS_BYTES>
+__device__ __forceinline__ void write_tile(const GemmParams &p, const v4f (&acc)[BM / WM / 16][BN / WN / 16], int m0,
+                                           int n0, int wave, int lane, int split, uint8_t *smem)
+{
+    constexpr int NW = WM * WN;
+    constexpr int WTM = BM / WM, WTN = BN / WN;
+    constexpr int TM = WTM / 16, TN = WTN / 16;
+    const int wm = wave / WN, wn = wave % WN;
+    const int lr = lane & 15, lg = lane >> 4;
+    if (p.splits > 1) {
+        static_for<0, TM>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            static_for<0, TN>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                const int ib = m0 + wm * WTM + i * 16 + (ALONG_J ? lr : 4 * lg);
+                const int jb = n0 + wn * WTN + j * 16 + (ALONG_J ? 4 * lg : lr);
+                store4<ALONG_J>(p, ib, jb, split, acc[i][j]);
+            });
+        });
+        return;
+    }
+    if (p.trans_out) write_tile_staged<BM, BN, WM, WN, ALONG_J, LDS_BYTES, true>(p, acc, m0, n0, wave, lane, smem);
+    else write_tile_staged<BM, BN, WM, WN, ALONG_J, LDS_BYTES, false>(p, acc, m0, n0, wave, lane, smem);
+}
+
 // One 16-byte load per lane from a buffer resource straight into LDS: lane l
 // writes LDS bytes [lds + 16 l, lds + 16 l + 16).  Issued from inline
 // assembly so that the compiler does not treat the pending LDS write as a
@@ -422,16 +568,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     }
 
     static_assert(!(SP && SWAP), "the compressed operand must stay in the MFMA A slot");
-    constexpr bool ALONG_J = SWAP;
-    static_for<0, TM>([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        static_for<0, TN>([&](auto jj) {
-            constexpr int j = decltype(jj)::value;
-            const int ib = m0 + wm * WTM + i * 16 + (ALONG_J ? lr : 4 * lg);
-            const int jb = n0 + wn * WTN + j * 16 + (ALONG_J ? 4 * lg : lr);
-            store4<ALONG_J>(p, ib, jb, split, acc[i][j]);
-        });
-    });
+    write_tile<BM, BN, WM, WN, SWAP, S::TOTAL>(p, acc, m0, n0, wave, lane, split, smem);
 }
 
 // Computes tile (tm, tn) of split `split`.  smem: TileSmem<BM,BN,SP>::TOTAL bytes.
@@ -788,16 +925,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
     // consecutive i of one j, consecutive in memory when the output is stored
     // transposed (compressed weight, or a dense weight-major problem).
     static_assert(!(SP && SWAP), "the compressed operand must stay in the MFMA A slot");
-    constexpr bool ALONG_J = SWAP;
-    static_for<0, TM>([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        static_for<0, TN>([&](auto jj) {
-            constexpr int j = decltype(jj)::value;
-            const int ib = m0 + wm * WTM + i * 16 + (ALONG_J ? lr : 4 * lg);
-            const int jb = n0 + wn * WTN + j * 16 + (ALONG_J ? 4 * lg : lr);
-            store4<ALONG_J>(p, ib, jb, split, acc[i][j]);
-        });
-    });
+    write_tile<BM, BN, WM, WN, SWAP, S::TOTAL>(p, acc, m0, n0, wave, lane, split, smem);
 }
 
 }  // namespace fp8k

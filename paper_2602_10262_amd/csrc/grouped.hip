@@ -1,96 +1,27 @@
-// Grouped FP8 GEMM: many independent dense and 2:4 problems in one persistent
-// launch, the batched form of a transformer-style sequence of FP8 GEMMs.
+// Grouped FP8 GEMM: many independent dense and 2:4 problems run by
+// persistent launches, the batched form of a transformer-style sequence of
+// FP8 GEMMs.  This file holds the plan (problem tables, tile choice, HIP
+// graph) and the launch sequence; the kernels are in grouped_kernel.hpp.
 //
-// Every problem runs weight-major: the weight (dense N x K rows, or its 2:4
-// compressed form) sits in the MFMA A slot and the activations (M x K) in the
-// B slot, the result being stored transposed into the row-major M x N output.
-// A tile therefore spans BM weight rows and BN tokens, so one tile shape fits
-// the whole mix of token counts and both kinds of problem.
-//
-// Work list: problems ordered by K, longest first; tile t of the list belongs
-// to the problem whose prefix sum of tiles brackets it.  Workgroups (one grid
-// sized to fill every CU) take tiles from a device counter with an atomic add
-// until the list is exhausted, which every workgroup reaches.  The counter is
-// cleared by a one-thread kernel in front of the persistent one, so the pair
-// can be captured into a HIP graph and replayed.
+// Work lists: the dense problems and the 2:4 problems form one list each,
+// ordered by K, longest first.  A grouped call clears both work counters
+// with one small kernel (so that a captured graph holds no memset node) and
+// launches the dense list's persistent kernel, then the 2:4 list's, on the
+// caller's stream.
 #include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "api_util.hpp"
-#include "gemm_tile.hpp"
+#include "grouped_kernel.hpp"
 
 namespace fp8k {
 
-__global__ void grouped_reset(unsigned long long *counter) { *counter = 0ull; }
-
-// Register budget of one workgroup per SIMD set: the kernel carries both the
-// dense and the 2:4 tile body, which the plain kernels' occupancy targets do
-// not fit (asking for them only makes the compiler spill and reschedule).
-template <int BM, int BN, int WM, int WN, int OCC, int PF, int FA, int FB>
-__global__ void __launch_bounds__(WM *WN * 64, 1)
-    grouped_kernel(const GroupEntry *__restrict__ table, int count, int64_t total, unsigned long long *counter)
+__global__ void grouped_reset(unsigned long long *counters, int n)
 {
-    constexpr int SMD = TileSmem<BM, BN, false, PF>::TOTAL, SMS = TileSmem<BM, BN, true, PF>::TOTAL;
-    __shared__ __attribute__((aligned(16))) uint8_t smem[SMD > SMS ? SMD : SMS];
-    __shared__ long long next;
-    for (;;) {
-        if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1ull);
-        __syncthreads();
-        const int64_t t = next;
-        __syncthreads();
-        if (t >= total) break;
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (table[mid].tile_begin <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        const GemmParams p = table[lo].p;
-        const int local = (int)(t - table[lo].tile_begin);
-        const int tiles_m = table[lo].tiles_m;
-        const int tm = local % tiles_m, tn = local / tiles_m;
-        if (table[lo].sparse)
-            gemm_tile<BM, BN, WM, WN, FA, FB, true, true, PF, false>(p, tm, tn, 0, smem);
-        else
-            gemm_tile<BM, BN, WM, WN, FA, FB, false, true, PF, false>(p, tm, tn, 0, smem);
-    }
+    if ((int)threadIdx.x < n) counters[threadIdx.x * 8] = 0ull;
 }
-
-template <int BM, int BN, int WM, int WN, int OCC, int PF>
-static hipError_t grouped_one(int fa, int fb, const GroupEntry *table, int count, int64_t total, int *counter,
-                              int grid, hipStream_t st)
-{
-    unsigned long long *c = reinterpret_cast<unsigned long long *>(counter);
-    grouped_reset<<<1, 1, 0, st>>>(c);
-    dim3 g((unsigned)grid), b(WM * WN * 64);
-    switch (fa * 2 + fb) {
-    case 0: grouped_kernel<BM, BN, WM, WN, OCC, PF, 0, 0><<<g, b, 0, st>>>(table, count, total, c); break;
-    case 1: grouped_kernel<BM, BN, WM, WN, OCC, PF, 0, 1><<<g, b, 0, st>>>(table, count, total, c); break;
-    case 2: grouped_kernel<BM, BN, WM, WN, OCC, PF, 1, 0><<<g, b, 0, st>>>(table, count, total, c); break;
-    default: grouped_kernel<BM, BN, WM, WN, OCC, PF, 1, 1><<<g, b, 0, st>>>(table, count, total, c); break;
-    }
-    return hipGetLastError();
-}
-
-// Tiles the grouped kernel is compiled for (a subset of the tile table: the
-// weight-row x token shapes that suit transformer mixes).
-#define FP8_GROUP_TILES(X) X(0) X(3) X(7) X(8) X(9) X(12) X(13) X(17) X(19) X(23)
-
-template <int T>
-struct TileArgs;
-#define FP8_TARGS(i, bm, bn, wm, wn, occ, pf)                                          \
-    template <>                                                                        \
-    struct TileArgs<i> {                                                               \
-        static hipError_t go(int fa, int fb, const GroupEntry *table, int count, int64_t total, \
-                             int *counter, int grid, hipStream_t st)                   \
-        {                                                                              \
-            return grouped_one<bm, bn, wm, wn, occ, pf>(fa, fb, table, count, total, counter, grid, st); \
-        }                                                                              \
-    };
-FP8_TILE_LIST(FP8_TARGS)
-#undef FP8_TARGS
 
 bool grouped_tile_supported(int tile)
 {
@@ -102,12 +33,14 @@ bool grouped_tile_supported(int tile)
     }
 }
 
-hipError_t launch_grouped(int tile, int fa, int fb, const GroupEntry *table, int count, int64_t total_tiles,
-                          int *counter, int grid, hipStream_t st)
+static hipError_t launch_list(int tile, bool sparse, int fa, int fb, const GroupEntry *table, int count,
+                              int64_t total, unsigned long long *counter, int grid, hipStream_t st)
 {
     switch (tile) {
-#define FP8_GCASE(i) \
-    case i: return TileArgs<i>::go(fa, fb, table, count, total_tiles, counter, grid, st);
+#define FP8_GCASE(i)                                                                              \
+    case i:                                                                                       \
+        return sparse ? grouped_launch_tile<i, true>(fa, fb, table, count, total, counter, grid, st) \
+                      : grouped_launch_tile<i, false>(fa, fb, table, count, total, counter, grid, st);
         FP8_GROUP_TILES(FP8_GCASE)
 #undef FP8_GCASE
     default: return hipErrorInvalidValue;
@@ -129,15 +62,34 @@ int grouped_max_workgroups(int tile)
 
 using namespace fp8k;
 
-struct fp8_grouped_plan {
-    int tile = 0, fa = 0, fb = 0, count = 0, grid = 0;
+// One work list: a contiguous range of the device table.
+struct GroupList {
+    int first = 0, count = 0, grid = 0;
     int64_t total_tiles = 0;
-    GroupEntry *d_table = nullptr;
-    int *d_counter = nullptr;
+};
+
+struct fp8_grouped_plan {
+    int tile = 0, fa = 0, fb = 0, count = 0;
+    GroupList list[2];                    // [0]: dense problems, [1]: 2:4 problems
+    GroupEntry *d_table = nullptr;        // dense entries, then 2:4 entries
+    unsigned long long *d_counters = nullptr;   // two counters, 64 bytes apart
     int use_graph = 0;
     bool captured = false;
     hipGraphExec_t exec = nullptr;
 };
+
+static hipError_t run_lists(const fp8_grouped_plan *plan, hipStream_t st)
+{
+    grouped_reset<<<1, 64, 0, st>>>(plan->d_counters, 2);
+    hipError_t e = hipGetLastError();
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        const GroupList &l = plan->list[k];
+        if (l.count == 0) continue;
+        e = launch_list(plan->tile, k == 1, plan->fa, plan->fb, plan->d_table + l.first, l.count, l.total_tiles,
+                        plan->d_counters + 8 * k, l.grid, st);
+    }
+    return e;
+}
 
 // Dense problem turned weight-major: C^T = W A^T with W = B^T (N x K rows).
 static void to_weight_major(Prepared &pr)
@@ -200,30 +152,35 @@ fp8_status fp8_grouped_plan_create(const fp8_group_problem *problems, int count,
     plan->count = count;
     plan->use_graph = use_graph;
     const TileDesc &td = tile_desc(plan->tile);
-    // longest tiles (largest K) first
+    // dense list first, then the 2:4 list; inside each, longest (largest K) first
     std::vector<int> order((size_t)count);
     for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return prs[x].p.K > prs[y].p.K; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (prs[x].sparse != prs[y].sparse) return !prs[x].sparse;
+        return prs[x].p.K > prs[y].p.K;
+    });
     std::vector<GroupEntry> table((size_t)count);
-    int64_t total = 0;
+    int cus = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     for (int k = 0; k < count; ++k) {
         const Prepared &pr = prs[order[k]];
+        GroupList &l = plan->list[pr.sparse ? 1 : 0];
+        if (l.count == 0) l.first = k;
         GroupEntry &e = table[k];
         std::memset(&e, 0, sizeof(e));
         e.p = pr.p;
         e.sparse = pr.sparse ? 1 : 0;
         e.tiles_m = (pr.p.M + td.bm - 1) / td.bm;
         e.tiles_n = (pr.p.N + td.bn - 1) / td.bn;
-        e.tile_begin = total;
-        total += (int64_t)e.tiles_m * e.tiles_n;
+        e.tile_begin = l.total_tiles;
+        l.total_tiles += (int64_t)e.tiles_m * e.tiles_n;
+        l.count++;
     }
-    plan->total_tiles = total;
-    int cus = 0, dev = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-    plan->grid = (int)std::min<int64_t>(total, (int64_t)cus * grouped_max_workgroups(plan->tile));
+    for (GroupList &l : plan->list)
+        l.grid = (int)std::min<int64_t>(l.total_tiles, (int64_t)cus * grouped_max_workgroups(plan->tile));
     hipError_t e = hipMalloc(&plan->d_table, sizeof(GroupEntry) * (size_t)count);
-    if (e == hipSuccess) e = hipMalloc(&plan->d_counter, 64);
+    if (e == hipSuccess) e = hipMalloc(&plan->d_counters, 128);
     if (e == hipSuccess)
         e = hipMemcpy(plan->d_table, table.data(), sizeof(GroupEntry) * (size_t)count, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -239,8 +196,7 @@ fp8_status fp8_grouped_gemm(fp8_grouped_plan *plan, void *stream)
     if (!plan) return set_error(FP8_ERR_ARG, "null plan");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (!plan->use_graph) {
-        hipError_t e = launch_grouped(plan->tile, plan->fa, plan->fb, plan->d_table, plan->count, plan->total_tiles,
-                                      plan->d_counter, plan->grid, st);
+        hipError_t e = run_lists(plan, st);
         return e == hipSuccess ? FP8_OK : hip_error(e, "grouped launch");
     }
     if (!st) return set_error(FP8_ERR_ARG, "graph mode needs a non-null stream");
@@ -248,8 +204,7 @@ fp8_status fp8_grouped_gemm(fp8_grouped_plan *plan, void *stream)
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_error(e, "begin capture");
-        hipError_t le = launch_grouped(plan->tile, plan->fa, plan->fb, plan->d_table, plan->count, plan->total_tiles,
-                                       plan->d_counter, plan->grid, st);
+        hipError_t le = run_lists(plan, st);
         e = hipStreamEndCapture(st, &graph);
         if (le != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -269,8 +224,8 @@ fp8_status fp8_grouped_plan_info(const fp8_grouped_plan *plan, int *tile, int64_
 {
     if (!plan) return set_error(FP8_ERR_ARG, "null plan");
     if (tile) *tile = plan->tile;
-    if (num_tiles) *num_tiles = plan->total_tiles;
-    if (num_workgroups) *num_workgroups = plan->grid;
+    if (num_tiles) *num_tiles = plan->list[0].total_tiles + plan->list[1].total_tiles;
+    if (num_workgroups) *num_workgroups = std::max(plan->list[0].grid, plan->list[1].grid);
     return FP8_OK;
 }
 
@@ -279,7 +234,7 @@ fp8_status fp8_grouped_plan_destroy(fp8_grouped_plan *plan)
     if (!plan) return FP8_OK;
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->d_table) (void)hipFree(plan->d_table);
-    if (plan->d_counter) (void)hipFree(plan->d_counter);
+    if (plan->d_counters) (void)hipFree(plan->d_counters);
     delete plan;
     return FP8_OK;
 }

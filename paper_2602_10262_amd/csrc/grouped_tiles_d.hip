@@ -1,0 +1,7 @@
+// Instantiates the grouped kernels of tiles 17 and 7 (dense and 2:4 lists).
+#include "grouped_kernel.hpp"
+
+namespace fp8k {
+FP8_GROUPED_INSTANTIATE(17)
+FP8_GROUPED_INSTANTIATE(7)
+}  // namespace fp8k

@@ -61,8 +61,7 @@ struct GroupEntry {
     int tiles_m, tiles_n;
     int64_t tile_begin;    // prefix sum of tiles over the work list
 };
-hipError_t launch_grouped(int tile, int fa, int fb, const GroupEntry *table, int count, int64_t total_tiles,
-                          int *counter, int grid, hipStream_t st);
 int grouped_max_workgroups(int tile);
+bool grouped_tile_supported(int tile);
 
 }  // namespace fp8k

@@ -105,6 +105,8 @@ struct Job {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double sim_done = 0;      // simulated executor: completion time
     double flops = 0;
+    bool queued = false;      // device work was enqueued (retire through ev1 even on failure)
+    fp8_status fail = FP8_OK; // failure to report when such a job retires
 };
 
 struct TicketState {
@@ -134,9 +136,6 @@ public:
     fp8_status start(Job &job, const Weight &w, uint8_t *arena, int stream) override
     {
         hipStream_t st = streams_[stream];
-        job.ev0 = take();
-        job.ev1 = take();
-        if (!job.ev0 || !job.ev1) return set_error(FP8_ERR_HIP, "event creation failed");
         const int64_t M = job.req.M, K = w.K;
         const int64_t ldq = (K + 15) / 16 * 16;
         uint8_t *q = arena + job.off;
@@ -144,29 +143,46 @@ public:
         float *d = s + align_f(M);
         void *ws = reinterpret_cast<uint8_t *>(d + align_f(M));
         const size_t ws_bytes = job.bytes - (size_t)((uint8_t *)ws - q);
-        (void)hipEventRecord(job.ev0, st);
-        fp8_status r = fp8_quantize(job.req.x, M, K, K, job.req.x_fmt, FP8_SCALE_ROW, q, ldq, s, d, nullptr, 0, st);
-        if (r != FP8_OK) return r;
+        // Every argument is checked before anything is enqueued: the GEMM's
+        // own validation runs through its workspace query on the final
+        // arguments, so a request that cannot run leaves no work behind.
         fp8_gemm_args g{};
         g.M = M; g.N = w.N; g.K = K;
         g.a_fmt = job.req.x_fmt; g.b_fmt = (fp8_fmt)w.fmt;
         g.a_descale = d; g.a_kind = FP8_SCALE_ROW;
         g.b_descale = w.descale; g.b_kind = FP8_SCALE_ROW;
         g.c = job.req.c; g.c_type = job.req.c_type; g.ldc = w.N;
+        fp8_sparse24_gemm_args sa{};
+        size_t need = 0;
+        fp8_status r;
         if (w.sparse) {
-            fp8_sparse24_gemm_args sa{};
             sa.g = g;
             sa.g.a = q; sa.g.lda = ldq;
             sa.side = FP8_SPARSE_B;
             sa.values = w.w; sa.meta = w.meta;
-            r = fp8_sparse24_gemm(&sa, nullptr, ws, ws_bytes, st);
+            r = fp8_sparse24_gemm_workspace_size(&sa, nullptr, &need);
         } else {
             g.a = q; g.lda = ldq;
             g.b = w.w; g.ldb = w.K;
-            r = fp8_gemm(&g, nullptr, ws, ws_bytes, st);
+            r = fp8_gemm_workspace_size(&g, nullptr, &need);
         }
         if (r != FP8_OK) return r;
+        if (need > ws_bytes) return set_error(FP8_ERR_ARG, "request workspace exceeds its arena range");
+        if (!job.req.x || (reinterpret_cast<uintptr_t>(job.req.x) & 15) || (K % 4))
+            return set_error(FP8_ERR_ALIGN, "activations must be 16-byte aligned with K % 4 == 0");
+        job.ev0 = take();
+        job.ev1 = take();
+        if (!job.ev0 || !job.ev1) return set_error(FP8_ERR_HIP, "event creation failed");
+        (void)hipEventRecord(job.ev0, st);
+        job.queued = true;
+        r = fp8_quantize(job.req.x, M, K, K, job.req.x_fmt, FP8_SCALE_ROW, q, ldq, s, d, nullptr, 0, st);
+        if (r == FP8_OK) r = w.sparse ? fp8_sparse24_gemm(&sa, nullptr, ws, ws_bytes, st)
+                                      : fp8_gemm(&g, nullptr, ws, ws_bytes, st);
+        // The completion event is recorded whatever happened above, so a job
+        // whose later launch failed is retired (and its arena range reused)
+        // only after the work already queued for it has finished.
         hipError_t e = hipEventRecord(job.ev1, st);
+        if (r != FP8_OK) return set_error(r, std::string("request launch failed after queueing: ") + fp8_last_error());
         return e == hipSuccess ? FP8_OK : hip_error(e, "event record");
     }
     bool finished(Job &job, double) override { return hipEventQuery(job.ev1) == hipSuccess; }
@@ -308,6 +324,18 @@ void scheduler(fp8_server *s)
             if (s->exec->finished(j, now)) {
                 const double t_done = s->simulated ? j.sim_done : now;
                 TicketState &ts = s->tickets[j.ticket];
+                if (j.fail != FP8_OK) {
+                    // a launch failed after part of the job was queued: its
+                    // arena range is reused only now that the queued work is done
+                    ts.status = j.fail;
+                    s->failed++;
+                    s->exec->release(j);
+                    s->arena.release(j.off, j.bytes);
+                    s->inflight[i] = s->inflight.back();
+                    s->inflight.pop_back();
+                    progress = true;
+                    continue;
+                }
                 ts.status = FP8_OK;
                 ts.latency_ms = (t_done - j.arrival) * 1e3;
                 s->latencies_ms.push_back(ts.latency_ms);
@@ -339,6 +367,13 @@ void scheduler(fp8_server *s)
             j.stream = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             const Weight &w = s->weights[(size_t)j.req.weight_id];
             fp8_status st = s->exec->start(j, w, s->arena_base, j.stream);
+            if (st != FP8_OK && j.queued) {
+                j.fail = st;
+                s->inflight.push_back(j);
+                s->pending.pop_front();
+                progress = true;
+                continue;
+            }
             if (st != FP8_OK) {
                 s->exec->release(j);
                 s->arena.release(j.off, j.bytes);
@@ -440,7 +475,14 @@ fp8_status fp8_server_register_weight(fp8_server *s, const uint8_t *w, const uin
     if (N < 1 || K < 1) return set_error(FP8_ERR_SHAPE, "N, K must be >= 1");
     if (fmt != FP8_E4M3 && fmt != FP8_E5M2) return set_error(FP8_ERR_ARG, "unknown format");
     if (!s->simulated && (!w || !w_descale)) return set_error(FP8_ERR_ARG, "null weight or descale");
+    // Weights the request path could never run are refused here, before any
+    // request queues work for them: a dense weight is read as N rows of K
+    // codes (leading dimension K, so K % 16 == 0), a 2:4 weight needs whole
+    // metadata bytes (K % 8 == 0); both need 16-byte aligned buffers.
     if (meta && K % 8) return set_error(FP8_ERR_SHAPE, "2:4 weight needs K % 8 == 0");
+    if (!meta && K % 16) return set_error(FP8_ERR_SHAPE, "dense weight needs K % 16 == 0");
+    auto misaligned = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; };
+    if (misaligned(w) || misaligned(meta)) return set_error(FP8_ERR_ALIGN, "weight buffers must be 16-byte aligned");
     std::lock_guard<std::mutex> lk(s->mu);
     Weight x;
     x.w = w; x.meta = meta; x.descale = w_descale; x.N = N; x.K = K; x.fmt = fmt; x.sparse = meta != nullptr;

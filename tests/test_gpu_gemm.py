@@ -43,7 +43,7 @@ def test_dense_ragged_shapes(gpu, M, N, K, fa, bf16):
     check_gemm(c, qa, fa, qb, 0, da, db, bf16, f"{M}x{N}x{K}")
 
 
-NUM_TILES = 25   # tile configurations the library exports (checked on the host)
+NUM_TILES = 25   # tile configurations the library exports (fp8_num_tiles)
 
 
 @pytest.mark.parametrize("tile", list(range(NUM_TILES)))

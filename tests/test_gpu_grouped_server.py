@@ -49,7 +49,7 @@ SPECS = [(1, 256, 512, False), (37, 384, 256, True), (200, 256, 1024, False), (5
          (300, 128, 384, True), (64, 640, 256, False), (17, 256, 768, False), (129, 256, 512, True)]
 
 
-@pytest.mark.parametrize("tile", [0, 3, 7, 8, 9, 12, 13, 17, 19, 23])
+@pytest.mark.parametrize("tile", [0, 7, 9, 12, 13, 17, 19, 23])
 def test_grouped_matches_oracle(gpu, tile):
     import torch
     probs = _mix(1, SPECS)
@@ -131,6 +131,9 @@ def test_server_results_same_alone_and_in_mix(gpu):
             c = torch.full((R["M"], Ws[R["w"]]["N"]), float("nan"), dtype=torch.bfloat16, device="cuda")
             keep.append(xd)
             outs[i] = c
+            # the server's streams are not ordered after torch's: x and c
+            # must be complete before the request is submitted
+            torch.cuda.current_stream().synchronize()
             tickets.append(srv.submit(R["M"], dev_w[R["w"]][0], xd, c))
         for t in tickets:
             assert srv.wait(t, 30_000_000) == gpu.FP8_OK
