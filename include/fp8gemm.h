@@ -122,6 +122,19 @@ fp8_status fp8_gemm_workspace_size(const fp8_gemm_args *args, const fp8_plan *pl
 fp8_status fp8_gemm(const fp8_gemm_args *args, const fp8_plan *plan, void *ws, size_t ws_bytes,
                     void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): fp8_gemm
+ * with the same arguments, plan choice and kernels, whose split-K partial
+ * sums live in a fixed device array of the library (fp8_noalloc_scratch_bytes()
+ * bytes per GPU, 32 MiB, held from the first call on a GPU until the process
+ * ends) instead of a workspace.  It calls no allocator.  A plan whose partial
+ * sums exceed that size is refused with FP8_ERR_UNSUPPORTED before anything is
+ * enqueued.  All calls on one GPU share that GPU's array: calls that overlap
+ * in time on one GPU race and must be ordered by the caller (one stream, or
+ * events).  Results equal fp8_gemm's with the same plan bit for bit. */
+size_t fp8_noalloc_scratch_bytes(void);
+fp8_status fp8_gemm_noalloc(const fp8_gemm_args *args, const fp8_plan *plan, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* 2:4 structured sparsity.                                                  */
 /* ------------------------------------------------------------------------ */

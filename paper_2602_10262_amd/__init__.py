@@ -74,6 +74,8 @@ _SIGS = {
     "fp8_gemm_plan_resolve": [_P, _P, _P],
     "fp8_gemm_workspace_size": [_P, _P, _P],
     "fp8_gemm": [_P, _P, _P, _SZ, _P],
+    "fp8_gemm_noalloc": [_P, _P, _P],
+    "fp8_noalloc_scratch_bytes": [],
     "fp8_sparse24_prune_compress": [_P, _I, _I64, _I64, _I64, _P, _P, _P, _P],
     "fp8_sparse24_decompress": [_P, _P, _I64, _I64, _P, _I64, _P],
     "fp8_sparse24_gemm_workspace_size": [_P, _P, _P],
@@ -102,6 +104,7 @@ _SIGS = {
     "fp8_validate": [_P, _I, _I64, _P, _P, _I64, _I64, _I64, _P, _P],
 }
 _RESTYPE = {"fp8_last_error": ctypes.c_char_p, "fp8_version": _I, "fp8_num_tiles": _I,
+            "fp8_noalloc_scratch_bytes": _SZ,
             "fp8_tune_cache_clear": None, "fp8_server_now": _D}
 
 _lib = None
@@ -225,6 +228,23 @@ def fp8_gemm(a, b_nk, a_descale, b_descale, a_fmt=FP8_E4M3, b_fmt=FP8_E4M3, out_
         nbytes = ws.numel() * ws.element_size()
     _call("fp8_gemm", ctypes.byref(args), pref, _ptr(ws), nbytes, _stream(stream))
     return c
+
+
+def fp8_gemm_noalloc(a, b_nk, a_descale, b_descale, a_fmt=FP8_E4M3, b_fmt=FP8_E4M3, out_dtype=None, c=None,
+                     plan=None, stream=None):
+    """fp8_gemm whose split-K partial sums use the library's fixed device
+    scratch array: the call itself allocates nothing (c must be given for
+    that; otherwise torch allocates it here)."""
+    import torch
+    if c is None:
+        c = torch.empty((a.shape[0], b_nk.shape[0]), dtype=out_dtype or torch.float32, device=a.device)
+    args = gemm_args(_u8(a), _u8(b_nk), a_descale, b_descale, c, a_fmt, b_fmt)
+    _call("fp8_gemm_noalloc", ctypes.byref(args), _plan(plan), _stream(stream))
+    return c
+
+
+def fp8_noalloc_scratch_bytes() -> int:
+    return int(load().fp8_noalloc_scratch_bytes())
 
 
 def fp8_gemm_plan_resolve(args: GemmArgs, plan=None) -> tuple:

@@ -89,3 +89,10 @@ def test_tuning_cache_roundtrip(tmp_path):
     assert '"tile": 3' in out.read_text()
     lib.fp8_tune_cache_clear()
     assert lib.fp8_gemm_plan_resolve(args) != (3, 2)
+
+
+def test_noalloc_entry_point_without_gpu():
+    L = lib.load()
+    assert L.fp8_noalloc_scratch_bytes() == 32 << 20
+    args = lib.GemmArgs()
+    assert L.fp8_gemm_noalloc(ctypes.byref(args), None, None) == 2  # FP8_ERR_SHAPE: M = 0
