@@ -146,6 +146,14 @@ fp8_plan heuristic_plan(const GemmKey &k)
 {
     fp8_plan p;
     const int64_t M = k.mk, N = k.nk;
+    if (k.kk < kExactBelowK) {
+        // exact-sum tiles: 128 x 128 once there are enough such tiles to fill
+        // the chip, else 64 x 64 (split-K below adds workgroups)
+        p.tile = cdiv(M, 128) * cdiv(N, 128) >= 256 ? 25 : 26;
+        const TileDesc &t = tile_desc(p.tile);
+        p.split_k = default_splits(cdiv(M, t.bm) * cdiv(N, t.bn), k.kk);
+        return p;
+    }
     if (N <= 16) p.tile = 8;
     else if (N <= 32) p.tile = 9;
     // single-wave 16 x 32 tiles on a 12-stage DMA ring: enough workgroups

@@ -6,7 +6,8 @@
 
 namespace fp8k {
 
-#define FP8_DESC(i, bm, bn, wm, wn, occ, pf) {bm, bn, wm * wn, tile_sparse_ok(bm) ? 1 : 0},
+#define FP8_DESC(i, bm, bn, wm, wn, occ, pf) \
+    {bm, bn, wm * wn, (tile_sparse_ok(bm) || pf == kExactPF) ? 1 : 0, pf == kExactPF ? 1 : 0},
 static const TileDesc kTiles[] = {FP8_TILE_LIST(FP8_DESC)};
 #undef FP8_DESC
 
@@ -19,7 +20,9 @@ hipError_t launch_gemm(int tile, int fa, int fb, bool sparse, const GemmParams &
 {
     // A K that leaves partial 16-byte chunks runs on the byte-exact loader,
     // compiled for the 128 x 128 tile only.
-    if (!k_is_fast(sparse, p.K)) return launch_one<128, 128, 2, 2, 1, 1, false>(fa, fb, sparse, p, st);
+    // (the exact-sum tiles load byte-exact themselves)
+    if (tile >= 0 && tile < num_tiles() && !tile_desc(tile).exact && !k_is_fast(sparse, p.K))
+        return launch_one<128, 128, 2, 2, 1, 1, false>(fa, fb, sparse, p, st);
     switch (tile) {
 #define FP8_CASE(i, bm, bn, wm, wn, occ, pf) \
     case i: return launch_tile<i>(fa, fb, sparse, p, st);

@@ -46,7 +46,7 @@ hipError_t launch_one(int fa, int fb, bool sp, const GemmParams &p, hipStream_t 
     const int nb = ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN);
     dim3 grid((unsigned)nb, 1, (unsigned)p.splits), block(WM * WN * 64);
 #define FP8_GO(FA, FB, SP) gemm_kernel<BM, BN, WM, WN, OCC, PF, FA, FB, SP, KFAST><<<grid, block, 0, st>>>(p)
-    if constexpr (tile_sparse_ok(BM)) {
+    if constexpr (tile_sparse_ok(BM) || PF == kExactPF) {
         const int key = fa * 4 + fb * 2 + (sp ? 1 : 0);
         switch (key) {
         case 0: FP8_GO(0, 0, false); break;

@@ -65,6 +65,8 @@ static fp8_status tune_prepared(const Prepared &pr, int iters, hipStream_t st, f
     for (int t = 0; t < num_tiles(); ++t) {
         const TileDesc &d = tile_desc(t);
         if (pr.sparse && !d.sparse_ok) continue;
+        // the accumulation class follows K (exact-sum tiles below kExactBelowK)
+        if ((d.exact != 0) != (pr.key.kk < kExactBelowK)) continue;
         const int64_t nb = ((pr.key.mk + d.bm - 1) / d.bm) * ((pr.key.nk + d.bn - 1) / d.bn);
         for (int s : {1, 2, 4, 8, 16, 32}) {
             if (s > steps) break;
