@@ -3,11 +3,13 @@
 // FP8 GEMMs.  This file holds the plan (problem tables, tile choice, HIP
 // graph) and the launch sequence; the kernels are in grouped_kernel.hpp.
 //
-// Work lists: the dense problems and the 2:4 problems form one list each,
-// ordered by K, longest first.  A grouped call clears both work counters
-// with one small kernel (so that a captured graph holds no memset node) and
-// launches the dense list's persistent kernel, then the 2:4 list's, on the
-// caller's stream.
+// Work lists: dense and 2:4 problems form lists of their own, and so do the
+// problems with K below kExactBelowK, which run on the exact-sum tile (FP8
+// decoded to BF16) so that their results meet the accuracy bound whatever
+// the data; each list is ordered by K, longest first.  A grouped call clears
+// the work counters with one small kernel (so that a captured graph holds no
+// memset node) and launches each non-empty list's persistent kernel in turn
+// on the caller's stream.
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -62,17 +64,20 @@ int grouped_max_workgroups(int tile)
 
 using namespace fp8k;
 
-// One work list: a contiguous range of the device table.
+// One work list: a contiguous range of the device table, run with one tile.
 struct GroupList {
-    int first = 0, count = 0, grid = 0;
+    int first = 0, count = 0, grid = 0, tile = 0;
     int64_t total_tiles = 0;
 };
 
+// List index: bit 0 = 2:4 problems, bit 1 = exact-sum tile (K below kExactBelowK).
+constexpr int kGroupLists = 4;
+
 struct fp8_grouped_plan {
     int tile = 0, fa = 0, fb = 0, count = 0;
-    GroupList list[2];                    // [0]: dense problems, [1]: 2:4 problems
-    GroupEntry *d_table = nullptr;        // dense entries, then 2:4 entries
-    unsigned long long *d_counters = nullptr;   // two counters, 64 bytes apart
+    GroupList list[kGroupLists];
+    GroupEntry *d_table = nullptr;        // the lists' entries, list by list
+    unsigned long long *d_counters = nullptr;   // one counter per list, 64 bytes apart
     int use_graph = 0;
     bool captured = false;
     hipGraphExec_t exec = nullptr;
@@ -80,12 +85,12 @@ struct fp8_grouped_plan {
 
 static hipError_t run_lists(const fp8_grouped_plan *plan, hipStream_t st)
 {
-    grouped_reset<<<1, 64, 0, st>>>(plan->d_counters, 2);
+    grouped_reset<<<1, 64, 0, st>>>(plan->d_counters, kGroupLists);
     hipError_t e = hipGetLastError();
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    for (int k = 0; k < kGroupLists && e == hipSuccess; ++k) {
         const GroupList &l = plan->list[k];
         if (l.count == 0) continue;
-        e = launch_list(plan->tile, k == 1, plan->fa, plan->fb, plan->d_table + l.first, l.count, l.total_tiles,
+        e = launch_list(l.tile, (k & 1) != 0, plan->fa, plan->fb, plan->d_table + l.first, l.count, l.total_tiles,
                         plan->d_counters + 8 * k, l.grid, st);
     }
     return e;
@@ -151,12 +156,13 @@ fp8_status fp8_grouped_plan_create(const fp8_group_problem *problems, int count,
     plan->fb = prs[0].fb;
     plan->count = count;
     plan->use_graph = use_graph;
-    const TileDesc &td = tile_desc(plan->tile);
-    // dense list first, then the 2:4 list; inside each, longest (largest K) first
+    auto list_of = [&](const Prepared &pr) { return (pr.sparse ? 1 : 0) + (pr.p.K < kExactBelowK ? 2 : 0); };
+    for (int k = 0; k < kGroupLists; ++k) plan->list[k].tile = (k & 2) ? kGroupExactTile : plan->tile;
+    // list by list; inside each, longest (largest K) first
     std::vector<int> order((size_t)count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        if (prs[x].sparse != prs[y].sparse) return !prs[x].sparse;
+        if (list_of(prs[x]) != list_of(prs[y])) return list_of(prs[x]) < list_of(prs[y]);
         return prs[x].p.K > prs[y].p.K;
     });
     std::vector<GroupEntry> table((size_t)count);
@@ -165,7 +171,8 @@ fp8_status fp8_grouped_plan_create(const fp8_group_problem *problems, int count,
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     for (int k = 0; k < count; ++k) {
         const Prepared &pr = prs[order[k]];
-        GroupList &l = plan->list[pr.sparse ? 1 : 0];
+        GroupList &l = plan->list[list_of(pr)];
+        const TileDesc &td = tile_desc(l.tile);
         if (l.count == 0) l.first = k;
         GroupEntry &e = table[k];
         std::memset(&e, 0, sizeof(e));
@@ -178,9 +185,9 @@ fp8_status fp8_grouped_plan_create(const fp8_group_problem *problems, int count,
         l.count++;
     }
     for (GroupList &l : plan->list)
-        l.grid = (int)std::min<int64_t>(l.total_tiles, (int64_t)cus * grouped_max_workgroups(plan->tile));
+        l.grid = (int)std::min<int64_t>(l.total_tiles, (int64_t)cus * grouped_max_workgroups(l.tile));
     hipError_t e = hipMalloc(&plan->d_table, sizeof(GroupEntry) * (size_t)count);
-    if (e == hipSuccess) e = hipMalloc(&plan->d_counters, 128);
+    if (e == hipSuccess) e = hipMalloc(&plan->d_counters, 64 * kGroupLists);
     if (e == hipSuccess)
         e = hipMemcpy(plan->d_table, table.data(), sizeof(GroupEntry) * (size_t)count, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -224,8 +231,14 @@ fp8_status fp8_grouped_plan_info(const fp8_grouped_plan *plan, int *tile, int64_
 {
     if (!plan) return set_error(FP8_ERR_ARG, "null plan");
     if (tile) *tile = plan->tile;
-    if (num_tiles) *num_tiles = plan->list[0].total_tiles + plan->list[1].total_tiles;
-    if (num_workgroups) *num_workgroups = std::max(plan->list[0].grid, plan->list[1].grid);
+    int64_t tiles = 0;
+    int grid = 0;
+    for (const GroupList &l : plan->list) {
+        tiles += l.total_tiles;
+        grid = std::max(grid, l.grid);
+    }
+    if (num_tiles) *num_tiles = tiles;
+    if (num_workgroups) *num_workgroups = grid;
     return FP8_OK;
 }
 

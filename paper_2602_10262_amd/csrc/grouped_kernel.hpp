@@ -81,8 +81,10 @@ hipError_t grouped_launch_tile(int fa, int fb, const GroupEntry *table, int coun
     }
 
 // Tiles the grouped kernels are compiled for (weight-row x token shapes that
-// suit transformer mixes; every one has a 2:4 body).
-#define FP8_GROUP_TILES(X) X(0) X(7) X(9) X(12) X(13) X(17) X(19) X(23)
+// suit transformer mixes; every one has a 2:4 body).  Tile 26 is the 64 x 64
+// exact-sum tile that problems with K below kExactBelowK run on.
+#define FP8_GROUP_TILES(X) X(0) X(7) X(9) X(12) X(13) X(17) X(19) X(23) X(26)
+constexpr int kGroupExactTile = 26;
 
 #define FP8_GROUPED_EXTERN(i)                                                                               \
     template <>                                                                                           \

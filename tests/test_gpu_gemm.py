@@ -178,7 +178,7 @@ def test_sparse_e5m2_activation(gpu):
 # ---------------------------------------------------- full-size samples ----
 
 @pytest.mark.parametrize("M,N,K,fa", [(8192, 8192, 8192, 0), (8192, 8192, 8192, 1), (16, 8192, 8192, 0),
-                                      (256, 8192, 8192, 1)])
+                                      (256, 8192, 8192, 1), (16384, 16384, 16384, 0), (16384, 16384, 16384, 1)])
 def test_full_size_sampled(gpu, M, N, K, fa):
     """The benchmark's shapes with the benchmark's default plan: sampled
     outputs against the oracle, N(0,1) + 1% 20-sigma outliers, per-row and
@@ -290,3 +290,34 @@ def test_fp8_mfma_tile_error_model_small_k(gpu, M, N, K, sparse):
     log(f"FP8 tile 0 M={M} N={N} K={K} sparse={sparse}: max err/bound={np.max(err / fp32_bound):.3f} "
         f"max err/envelope={np.max(err / envelope):.3f}")
     assert np.all(err <= envelope)
+
+
+# ------------------------------------------------------ device validator ---
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_device_validator_agrees_with_oracle_check(gpu, bf16):
+    """fp8_validate (FP64 reduction on the GPU) reports the same maximum error,
+    maximum ratio to the bound, normwise error and count over the bound as the
+    oracle's CPU check of the same result; a planted error is counted by both."""
+    import torch
+    M, N, K = 300, 200, 1000
+    qa, da, qb, db = operands(M, N, K, 23, "normal", 0, 0, True)
+    c = _run_dense(gpu, qa, qb, da, db, 0, 0, bf16)
+    cref, sabs = orc.gemm(qa, 0, qb, 0, da, db)
+    out_t = orc.OUT_BF16 if bf16 else orc.OUT_F32
+    for planted in (False, True):
+        if planted:
+            # push a few outputs far outside their bound
+            c.view(-1)[torch.tensor([0, 777, M * N - 1], device="cuda")] += 1.0
+            torch.cuda.synchronize()
+        ref = orc.check(host(c), cref, sabs, K, out_t)
+        got = gpu.fp8_validate(c, dev(cref), dev(sabs), K)
+        torch.cuda.synchronize()
+        b = orc.bound(sabs, cref, K, out_t)
+        over = int(np.sum(np.abs(host(c).astype(np.float64) - cref) > b))
+        log(f"validator bf16={bf16} planted={planted}: gpu {got} cpu {ref} over {over}")
+        assert got["over"] == over
+        assert got["ok"] == ref["ok"] == (not planted)
+        assert np.isclose(got["max_abs_err"], ref["max_abs_err"], rtol=1e-12, atol=0)
+        assert np.isclose(got["max_ratio"], ref["max_ratio"], rtol=1e-12, atol=0)
+        assert np.isclose(got["normwise"], ref["normwise"], rtol=1e-9, atol=0)

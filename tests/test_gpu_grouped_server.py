@@ -4,7 +4,7 @@ import pytest
 
 import oracle as orc
 from paper_2602_10262_amd import synth
-from tests.helpers import check_gemm, dev, host, log
+from tests.helpers import check_gemm, check_gemm_sampled, dev, host, log
 
 pytestmark = pytest.mark.gpu
 
@@ -45,14 +45,18 @@ def _gproblems(gpu, probs):
     return out
 
 
+# small K: these run on the exact-sum list whatever the plan's tile
 SPECS = [(1, 256, 512, False), (37, 384, 256, True), (200, 256, 1024, False), (5, 512, 512, True),
          (300, 128, 384, True), (64, 640, 256, False), (17, 256, 768, False), (129, 256, 512, True)]
+# K >= 3584: these run on the plan's FP8 tile
+SPECS_LONG_K = [(1, 256, 4096, False), (37, 384, 3584, True), (200, 256, 4096, False), (5, 512, 4096, True),
+                (300, 128, 3712, True), (64, 640, 3600, False)]
 
 
-@pytest.mark.parametrize("tile", [0, 7, 9, 12, 13, 17, 19, 23])
+@pytest.mark.parametrize("tile", [0, 7, 9, 12, 13, 17, 19, 23, 26])
 def test_grouped_matches_oracle(gpu, tile):
     import torch
-    probs = _mix(1, SPECS)
+    probs = _mix(1, SPECS + SPECS_LONG_K)
     plan = gpu.GroupedPlan(_gproblems(gpu, probs), tile=tile)
     log(f"grouped tile={tile} info={plan.info()}")
     plan.run()
@@ -151,3 +155,44 @@ def test_server_results_same_alone_and_in_mix(gpu):
         R, W = reqs[i], Ws[reqs[i]["w"]]
         qa, _, da = orc.quantize(R["x"], 0, True)
         check_gemm(mix[i], qa, 0, W["qw"], 0, da, W["dw"], True, f"request {i} M={R['M']}")
+
+
+def test_grouped_config4_shapes_match_standalone_and_oracle(gpu):
+    """Transformer-shaped problems of the grouped workload (tokens up to 4096,
+    (N, K) from the four weight shapes, half of them 2:4 on the weight side)
+    in one grouped plan with the library's default tile: every problem's
+    result equals the same problem run by fp8_gemm / fp8_sparse24_gemm with
+    that tile and no split, bit for bit, and sampled outputs meet the bound
+    against the oracle."""
+    import torch
+    specs = [(4096, 14336, 4096, False), (300, 4096, 14336, True), (1, 4096, 4096, False), (17, 12288, 4096, True),
+             (1000, 4096, 14336, False), (64, 14336, 4096, True), (2048, 12288, 4096, False), (5, 4096, 4096, True)]
+    probs = []
+    for i, (M, N, K, sparse) in enumerate(specs):
+        xa = synth.normal_outliers(7000 + 2 * i, (M, K))
+        xw = synth.normal_outliers(7001 + 2 * i, (N, K))
+        qa, _, da = orc.quantize(xa, 0, True)
+        qw, _, dw = orc.quantize(xw, 0, True)
+        del xa, xw
+        v = m = None
+        if sparse:
+            v, m, _, qw = orc.prune24(qw, 0)
+        probs.append(dict(M=M, N=N, K=K, sparse=sparse, qa=qa, da=da, qw=qw, dw=dw, v=v, m=m))
+    plan = gpu.GroupedPlan(_gproblems(gpu, probs))
+    info = plan.info()
+    log(f"grouped config-4 subset: {info}")
+    plan.run()
+    torch.cuda.synchronize()
+    tile = info["tile"]
+    for p in probs:
+        a, da, dw = p["keep"][0], p["keep"][-2], p["keep"][-1]
+        if p["sparse"]:
+            alone = gpu.fp8_sparse24_gemm(p["keep"][1], p["keep"][2], a, gpu.FP8_SPARSE_B, da, dw,
+                                          out_dtype=torch.bfloat16, plan=(tile, 1))
+        else:
+            alone = gpu.fp8_gemm(a, p["keep"][1], da, dw, out_dtype=torch.bfloat16, plan=(tile, 1))
+        torch.cuda.synchronize()
+        what = f"M={p['M']} N={p['N']} K={p['K']} sparse={p['sparse']}"
+        assert torch.equal(alone.view(torch.int16), p["c"].view(torch.int16)), what
+        check_gemm_sampled(p["c"], p["qa"], 0, p["qw"], 0, p["da"], p["dw"], True, n=512, what="grouped " + what)
+    plan.close()
