@@ -373,9 +373,12 @@ def bench_grouped(lib, stream, seed=0, count=64):
     return res
 
 
-def bench_served(lib, n_requests=20000, seed=0, rates=(0.5, 1.0, 1.5), budget=2 << 30, streams=4, slots=32):
+def bench_served(lib, n_requests=20000, seed=0, rates=(0.5, 1.0, 1.5), budget=2 << 30, streams=4, slots=64):
     """Poisson stream of dense / 2:4 GEMM requests through the server on
-    `streams` streams against the same arrivals served one at a time."""
+    `streams` streams against the same arrivals served one at a time.
+    Request r writes output slot r % slots; before it is submitted, the
+    request that last used that slot has completed (slots exceeds the number
+    of requests in flight), so no two live requests share an output."""
     import torch
     from paper_2602_10262_amd import synth
     rng = np.random.default_rng(seed)
@@ -392,6 +395,7 @@ def bench_served(lib, n_requests=20000, seed=0, rates=(0.5, 1.0, 1.5), budget=2 
             weights[(N, K)] = (qw, v, m, dw)
     pools = {K: torch.from_numpy(synth.uniform(seed, K, (Mmax, K))).cuda() for K in sizes}
     out_slots = [torch.empty(Mmax * max(sizes), dtype=torch.bfloat16, device="cuda") for _ in range(slots)]
+    torch.cuda.synchronize()   # the server's streams are not ordered after torch's
     Ms = synth.log_uniform_int(rng, 1, Mmax, n_requests)
     Ns = rng.choice(sizes, n_requests)
     Ks = rng.choice(sizes, n_requests)
@@ -410,6 +414,9 @@ def bench_served(lib, n_requests=20000, seed=0, rates=(0.5, 1.0, 1.5), budget=2 
         for r in range(n_requests):
             M, N, K = int(Ms[r]), int(Ns[r]), int(Ks[r])
             x_ptr = pools[K].data_ptr() + offs[r] * K * 4
+            if r >= slots:
+                # the slot's previous request must be done before its output is reused
+                srv.wait(tickets[r - slots], -1)
             tickets.append(srv.submit(M, ids[(N, K, bool(sp[r]))], x_ptr=x_ptr,
                                       c_ptr=out_slots[r % slots].data_ptr(),
                                       arrival_time_s=t0 + float(arrivals[r])))
