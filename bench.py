@@ -112,94 +112,190 @@ def cpu_baseline(M, N, K, target_s=20.0):
             "sample": f"{done_rows} of {M} rows of the {M}x{N}x{K} GEMM (FP64, exact decode), {spent:.1f} s"}
 
 
-def bench_ace(lib, base, size=512, iters=100, counts=(1, 2, 4, 8)):
-    """Concurrent-stream study at size^3: `n` streams each run `iters`
-    back-to-back GEMMs (dense, 2:4 on A, or half of the streams each) from a
-    common start event.  Each stream's GEMMs are captured once into a HIP
-    graph, so the host launch rate does not limit what the device overlaps;
-    one replay per graph is checked bit for bit against the eager result.
-    Per stream: time from the start to its last GEMM.  Reported per
-    (mode, n): makespan, aggregate dense-equivalent TFLOP/s, speedup = (sum of
-    each stream's own one-stream time) / makespan, overlap (share of the makespan with at
-    least two streams still running: the second-latest stream end over the
-    latest), the coefficient of variation of the stream times and both
-    fairness measures."""
+def overlap_fraction(spans):
+    """Share of the makespan during which at least two of the (start, end)
+    intervals are active: the paper's overlap efficiency (Sec. 4.2), here over
+    the streams' busy spans (each stream runs its kernels back to back)."""
+    if len(spans) < 2:
+        return 0.0
+    ev = sorted([(s, 1) for s, _ in spans] + [(e, -1) for _, e in spans])
+    t0 = min(s for s, _ in spans)
+    t1 = max(e for _, e in spans)
+    active, last, both = 0, t0, 0.0
+    for t, d in ev:
+        if active >= 2:
+            both += t - last
+        active += d
+        last = t
+    return both / (t1 - t0) if t1 > t0 else 0.0
+
+
+def fp8_plan_sweep(lib, fn_plan, stream, candidates):
+    """The fastest FP8-MFMA plan of `candidates` for fn_plan(plan)."""
+    best = None
+    for pl in candidates:
+        try:
+            fn_plan(pl)
+        except lib.Fp8Error:
+            continue
+        ms = time_events(lambda: fn_plan(pl), 10, stream)
+        if best is None or ms < best[1]:
+            best = (pl, ms)
+    return best
+
+
+def bench_ace(lib, base, sizes=(256, 512, 2048), iters=100, counts=(1, 2, 4, 8), pairs_with=(512, 1024, 2048)):
+    """Concurrent-stream study (the paper's ACE study, Sec. 6): at each size,
+    `n` streams each run `iters` back-to-back GEMMs (dense, 2:4 on A, or half
+    of the streams each), every stream's GEMMs captured once into a HIP graph
+    so the host launch rate does not limit what the device overlaps.  The
+    GEMMs run FP8-MFMA plans (the path this study is about; below K = 3584
+    the library's own default is the exact-sum path) picked by a small sweep.
+    Per stream: device time from its first kernel to its last (events on the
+    stream).  Reported per (size, mode, n): makespan, aggregate TFLOP/s,
+    speedup (the streams' one-stream times, summed, over the makespan),
+    overlap (share of the makespan with at least two streams busy), the
+    coefficient of variation of the stream times and both fairness measures.
+    Co-run pairs (occupancy fragmentation, Sec. 6.3): a 512^3 stream beside a
+    stream of S^3 GEMMs sized to the same one-stream time."""
     import torch
     from paper_2602_10262_amd import synth
-    M = N = K = size
-    xa = torch.from_numpy(synth.normal_outliers(7, (M, K))).cuda()
-    xb = torch.from_numpy(synth.normal_outliers(8, (N, K))).cuda()
-    qa, _, da = lib.fp8_quantize(xa, 0, lib.FP8_SCALE_ROW, stream=base)
-    qb, _, db = lib.fp8_quantize(xb, 0, lib.FP8_SCALE_ROW, stream=base)
-    va, ma, _ = lib.fp8_sparse24_prune_compress(qa, 0, with_mask=False, stream=base)
-    torch.cuda.synchronize()
-    flops = 2.0 * M * N * K
     nmax = max(counts)
-    outs = [torch.empty((M, N), dtype=torch.bfloat16, device="cuda") for _ in range(nmax)]
     streams = [torch.cuda.Stream() for _ in range(nmax)]
+    res = {"iters_per_stream": iters, "launch": "one HIP graph per stream", "sizes": {}}
+    ops = {}
 
-    def gemm(sparse, i, st):
-        if sparse:
-            lib.fp8_sparse24_gemm(va, ma, qb, lib.FP8_SPARSE_A, da, db, c=outs[i], stream=st)
-        else:
-            lib.fp8_gemm(qa, qb, da, db, c=outs[i], stream=st)
-
-    ref = {}
-    for sparse in (False, True):
-        gemm(sparse, 0, base)
+    def operands(size):
+        if size in ops:
+            return ops[size]
+        M = N = K = size
+        xa = torch.from_numpy(synth.normal_outliers(7, (M, K))).cuda()
+        xb = torch.from_numpy(synth.normal_outliers(8, (N, K))).cuda()
+        qa, _, da = lib.fp8_quantize(xa, 0, lib.FP8_SCALE_ROW, stream=base)
+        qb, _, db = lib.fp8_quantize(xb, 0, lib.FP8_SCALE_ROW, stream=base)
+        va, ma, _ = lib.fp8_sparse24_prune_compress(qa, 0, with_mask=False, stream=base)
         torch.cuda.synchronize()
-        ref[sparse] = outs[0].clone()
-    graphs = {}
-    for mode in ("dense", "sparse", "mixed"):
-        for i in range(nmax):
-            sparse = mode == "sparse" or (mode == "mixed" and i % 2 == 1)
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=streams[i]):
-                for _ in range(iters):
-                    gemm(sparse, i, streams[i])
-            outs[i].zero_()
-            with torch.cuda.stream(streams[i]):
-                g.replay()
-            torch.cuda.synchronize()
-            if not torch.equal(outs[i], ref[sparse]):
-                raise RuntimeError(f"graph replay differs from the eager GEMM ({mode}, stream {i})")
-            graphs[(mode, i)] = g
+        cands = [(t, s) for t in (0, 3, 7, 8, 13, 19) for s in (1, 2, 4)]
+        c0 = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+        dplan = fp8_plan_sweep(lib, lambda pl: lib.fp8_gemm(qa, qb, da, db, c=c0, plan=pl, stream=base), base, cands)[0]
+        splan = fp8_plan_sweep(lib, lambda pl: lib.fp8_sparse24_gemm(va, ma, qb, lib.FP8_SPARSE_A, da, db, c=c0,
+                                                                     plan=pl, stream=base), base, cands)[0]
+        outs = [torch.empty((M, N), dtype=torch.bfloat16, device="cuda") for _ in range(nmax)]
+        ws = [torch.empty(4 * M * N * 4, dtype=torch.uint8, device="cuda") for _ in range(nmax)]
+        ops[size] = dict(qa=qa, qb=qb, da=da, db=db, va=va, ma=ma, dplan=dplan, splan=splan, outs=outs, ws=ws)
+        return ops[size]
 
-    def run(n, mode):
+    def gemm(size, sparse, i, st):
+        o = operands(size)
+        if sparse:
+            lib.fp8_sparse24_gemm(o["va"], o["ma"], o["qb"], lib.FP8_SPARSE_A, o["da"], o["db"], c=o["outs"][i],
+                                  plan=o["splan"], ws=o["ws"][i], stream=st)
+        else:
+            lib.fp8_gemm(o["qa"], o["qb"], o["da"], o["db"], c=o["outs"][i], plan=o["dplan"], ws=o["ws"][i], stream=st)
+
+    def capture(size, sparse, i, n_iter):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=streams[i]):
+            for _ in range(n_iter):
+                gemm(size, sparse, i, streams[i])
+        return g
+
+    def run(graphs):
+        """graphs[i] runs on stream i; returns per-stream (start, end) in ms from a common event."""
+        n = len(graphs)
         start = torch.cuda.Event(enable_timing=True)
+        begins = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
         ends = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
         start.record(base)
         for i in range(n):
             streams[i].wait_event(start)
+            begins[i].record(streams[i])
             with torch.cuda.stream(streams[i]):
-                graphs[(mode, i)].replay()
+                graphs[i].replay()
             ends[i].record(streams[i])
         torch.cuda.synchronize()
-        return [start.elapsed_time(e) for e in ends]
+        return [(start.elapsed_time(b), start.elapsed_time(e)) for b, e in zip(begins, ends)]
 
-    res = {"size": size, "iters_per_stream": iters, "launch": "one HIP graph per stream", "modes": {}}
-    alone = {}
-    for mode in ("dense", "sparse"):
-        run(1, mode)   # warm-up
-        alone[mode] = run(1, mode)[0]
-    for mode in ("dense", "sparse", "mixed"):
-        one = alone["dense" if mode == "mixed" else mode]
-        rows = []
-        for n in counts:
-            t = run(n, mode)
-            mk = max(t)
-            srt = sorted(t)
-            mean = sum(t) / n
-            sd = (sum((x - mean) ** 2 for x in t) / n) ** 0.5
-            # speedup: the streams' own one-stream times, summed, over the makespan
-            serial = sum(alone["sparse" if (mode == "sparse" or (mode == "mixed" and i % 2 == 1)) else "dense"]
-                         for i in range(n))
-            rows.append({"streams": n, "makespan_ms": mk, "tflops": n * iters * flops / (mk * 1e-3) / 1e12,
-                         "speedup": serial / mk, "overlap": (srt[-2] / mk) if n > 1 else 0.0,
-                         "cv": sd / mean, "fairness_range": 1.0 - (srt[-1] - srt[0]) / mean,
-                         "fairness_minmax": srt[0] / srt[-1]})
-        res["modes"][mode] = {"one_stream_ms": one, "rows": rows}
-    del graphs
+    def stats(spans, alone):
+        t = [e - s for s, e in spans]
+        mk = max(e for _, e in spans) - min(s for s, _ in spans)
+        mean = sum(t) / len(t)
+        sd = (sum((x - mean) ** 2 for x in t) / len(t)) ** 0.5
+        return {"makespan_ms": mk, "speedup": sum(alone) / mk, "overlap": overlap_fraction(spans),
+                "cv": sd / mean, "fairness_range": 1.0 - (max(t) - min(t)) / mean, "fairness_minmax": min(t) / max(t),
+                "stream_ms": t}
+
+    for size in sizes:
+        o = operands(size)
+        flops = 2.0 * size ** 3
+        # each stream's graph checked once against the eager GEMM, bit for bit
+        ref = {}
+        for sparse in (False, True):
+            gemm(size, sparse, 0, base)
+            torch.cuda.synchronize()
+            ref[sparse] = o["outs"][0].clone()
+        graphs = {}
+        for mode in ("dense", "sparse", "mixed"):
+            for i in range(nmax):
+                sparse = mode == "sparse" or (mode == "mixed" and i % 2 == 1)
+                g = capture(size, sparse, i, iters)
+                o["outs"][i].zero_()
+                with torch.cuda.stream(streams[i]):
+                    g.replay()
+                torch.cuda.synchronize()
+                if not torch.equal(o["outs"][i], ref[sparse]):
+                    raise RuntimeError(f"graph replay differs from the eager GEMM ({size}, {mode}, stream {i})")
+                graphs[(mode, i)] = g
+        alone = {}
+        for mode in ("dense", "sparse"):
+            run([graphs[(mode, 0)]])
+            sp = run([graphs[(mode, 0)]])[0]
+            alone[mode] = sp[1] - sp[0]
+        sres = {"plans": {"dense": list(o["dplan"]), "sparse": list(o["splan"])},
+                "one_stream_ms": dict(alone), "modes": {}}
+        for mode in ("dense", "sparse", "mixed"):
+            rows = []
+            for n in counts:
+                kinds = ["sparse" if (mode == "sparse" or (mode == "mixed" and i % 2 == 1)) else "dense"
+                         for i in range(n)]
+                spans = run([graphs[(mode, i)] for i in range(n)])
+                row = stats(spans, [alone[k] for k in kinds])
+                row.update({"streams": n, "tflops": n * iters * flops / (row["makespan_ms"] * 1e-3) / 1e12})
+                rows.append(row)
+            sres["modes"][mode] = rows
+        res["sizes"][str(size)] = sres
+        log(f"  ace {size}^3: " + "; ".join(
+            f"{m} " + ", ".join(f"{r['streams']}s x{r['speedup']:.2f} ov {r['overlap']:.2f}" for r in rows)
+            for m, rows in sres["modes"].items()))
+        del graphs
+    # co-run pairs: 512^3 beside S^3 of about the same one-stream time
+    if 512 in sizes:
+        pres = []
+        g512 = capture(512, False, 0, iters)
+        run([g512])
+        sp = run([g512])[0]
+        t512 = sp[1] - sp[0]
+        for S in pairs_with:
+            operands(S)
+            probe = capture(S, False, 1, 10)
+            run([probe])
+            sp = run([probe])[0]
+            per = (sp[1] - sp[0]) / 10
+            n_it = max(1, int(round(t512 / per)))
+            gS = capture(S, False, 1, n_it)
+            run([gS])
+            spS = run([gS])[0]
+            tS = spS[1] - spS[0]
+            spans = run([g512, gS])
+            row = stats(spans, [t512, tS])
+            row.update({"pair": f"512^3 x {iters} with {S}^3 x {n_it}",
+                        "slowdown_512": (spans[0][1] - spans[0][0]) / t512,
+                        "slowdown_other": (spans[1][1] - spans[1][0]) / tS})
+            pres.append(row)
+            del gS, probe
+        res["pairs"] = pres
+        log("  ace pairs: " + "; ".join(f"{r['pair']}: x{r['speedup']:.2f} fair {r['fairness_minmax']:.2f}"
+                                        for r in pres))
     return res
 
 
@@ -250,7 +346,11 @@ def bench_shape(lib, M, N, K, fa, stream, iters=20, tune=True, rotate=1, sparse_
     values, meta, _ = lib.fp8_sparse24_prune_compress(qa, fa, with_mask=False)
     pruned = lib.fp8_sparse24_decompress(values, meta, K)
     gargs = lib.gemm_args(pruned, qb, da, db, c, fa, 0)
-    if tune:
+    if tune and sparse_too:
+        # dense on the pruned A against 2:4 on A: both tuned, record kept by the library
+        sargs0 = lib.sparse24_args(values, meta, qb, lib.FP8_SPARSE_A, da, db, c, fa, 0)
+        res["breakeven_A"] = lib.fp8_tune_sparse_vs_dense(sargs0, gargs, iters=3, stream=stream)
+    elif tune:
         lib.fp8_tune_gemm(gargs, iters=3, stream=stream)
     it = [0]
 
@@ -285,7 +385,9 @@ def bench_shape(lib, M, N, K, fa, stream, iters=20, tune=True, rotate=1, sparse_
         wv, wm, _ = lib.fp8_sparse24_prune_compress(qb, 0, with_mask=False)
         wargs = lib.sparse24_args(wv, wm, qa, lib.FP8_SPARSE_B, da, db, c, 0, fa)
         if tune:
-            lib.fp8_tune_sparse24_gemm(wargs, iters=3, stream=stream)
+            wpruned = lib.fp8_sparse24_decompress(wv, wm, K)
+            res["breakeven_B"] = lib.fp8_tune_sparse_vs_dense(wargs, lib.gemm_args(qa, wpruned, da, db, c, fa, 0),
+                                                              iters=3, stream=stream)
         wms = time_events(lambda: lib.fp8_sparse24_gemm(wv, wm, qa, lib.FP8_SPARSE_B, da, db, 0, fa, c=c,
                                                         stream=stream), iters, stream)
         res["weight_sparse_ms"] = wms
@@ -348,20 +450,23 @@ def bench_grouped(lib, stream, seed=0, count=64):
     plain_ms = time_events(run_plain, 5, stream)
     res["plain_ms"] = plain_ms
     res["plain_tflops"] = flops / plain_ms / 1e9
-    best = None
-    for tile in (9, 12, 13, 0, 7, 17, 19, 23):
-        plan = lib.GroupedPlan(probs, tile=tile, use_graph=True)
-        plan.run(stream)
-        ms = time_events(lambda: plan.run(stream), 5, stream)
-        res[f"grouped_ms_tile{tile}"] = ms
-        if best is None or ms < best[1]:
-            best = (tile, ms, plan.info())
-        plan.close()
-    res["grouped_tile"] = best[0]
-    res["grouped_info"] = best[2]
-    res["grouped_ms"] = best[1]
-    res["grouped_tflops"] = flops / best[1] / 1e9
-    res["speedup_vs_plain"] = plain_ms / best[1]
+    # the library's grouped tuner picks the tile; the plan then replays from a HIP graph
+    tile, tune_us = lib.fp8_grouped_tune(probs, iters=5, stream=stream)
+    res["tuner"] = {"tile": tile, "median_us": tune_us}
+    plan = lib.GroupedPlan(probs, tile=tile, use_graph=True)
+    plan.run(stream)
+    ms = time_events(lambda: plan.run(stream), 5, stream)
+    res["grouped_tile"] = tile
+    res["grouped_info"] = plan.info()
+    plan.close()
+    default_plan = lib.GroupedPlan(probs, use_graph=True)
+    default_plan.run(stream)
+    res["default_tile"] = default_plan.info()["tile"]
+    res["default_ms"] = time_events(lambda: default_plan.run(stream), 5, stream)
+    default_plan.close()
+    res["grouped_ms"] = ms
+    res["grouped_tflops"] = flops / ms / 1e9
+    res["speedup_vs_plain"] = plain_ms / ms
     # rooflines of the drawn instance: each problem alone at its own bound,
     # and all of them overlapped
     f_g = 2.0 * Ms * np.array([n for n, _ in nk]) * np.array([k for _, k in nk])
@@ -373,7 +478,7 @@ def bench_grouped(lib, stream, seed=0, count=64):
     return res
 
 
-def bench_served(lib, n_requests=20000, seed=0, rates=(0.5, 1.0, 1.5), budget=2 << 30, streams=4, slots=64):
+def bench_served(lib, n_requests=20000, seed=0, rates=(0.5, 1.0, 1.5), budgets=(2 << 30,), streams=4, slots=64):
     """Poisson stream of dense / 2:4 GEMM requests through the server on
     `streams` streams against the same arrivals served one at a time.
     Request r writes output slot r % slots; before it is submitted, the
@@ -403,7 +508,7 @@ def bench_served(lib, n_requests=20000, seed=0, rates=(0.5, 1.0, 1.5), budget=2 
     offs = [int(rng.integers(0, Mmax - M + 1)) for M in Ms]
     flops = float(np.sum(2.0 * Ms * Ns * Ks))
 
-    def run(arrivals, nstreams, max_inflight):
+    def run(arrivals, nstreams, max_inflight, budget=budgets[0]):
         srv = lib.Server(budget, nstreams, max_inflight)
         ids = {}
         for (N, K), (qw, v, m, dw) in weights.items():
@@ -429,21 +534,49 @@ def bench_served(lib, n_requests=20000, seed=0, rates=(0.5, 1.0, 1.5), budget=2 
     cap = run(np.zeros(n_requests), 1, 1)
     mu = n_requests / cap["span_s"]
     res = {"requests": n_requests, "flops": flops, "serial_capacity_req_s": mu,
-           "serial_capacity_tflops": cap["tflops"], "streams": streams, "budget_bytes": budget, "rates": []}
+           "serial_capacity_tflops": cap["tflops"], "streams": streams, "budgets_bytes": list(budgets), "rates": []}
+    # per-stream busy-time balance under least-loaded placement (the streams
+    # carry different work, so this is a load-balance figure, not the paper's
+    # fairness over equal per-stream workloads, which the ACE study reports)
+    keys = ("p50_ms", "p99_ms", "mean_ms", "tflops", "stream_cv", "peak_inflight", "peak_bytes", "done")
     for f in rates:
         lam = f * mu
         arr = synth.poisson_arrivals(np.random.default_rng(seed + 1), lam, n_requests)
-        served = run(arr, streams, 4 * streams)
         serial = run(arr, 1, 1)
-        keys = ("p50_ms", "p99_ms", "mean_ms", "tflops", "stream_cv", "fairness_range", "fairness_minmax",
-                "peak_inflight", "peak_bytes", "done")
-        res["rates"].append({"load": f, "rate_req_s": lam,
-                             "served": {k: served[k] for k in keys},
-                             "serial": {k: serial[k] for k in keys}})
-        log(f"served load {f}: p50 {served['p50_ms']:.2f} ms p99 {served['p99_ms']:.2f} ms "
-            f"{served['tflops']:.0f} TF/s | serial p50 {serial['p50_ms']:.2f} p99 {serial['p99_ms']:.2f} "
-            f"{serial['tflops']:.0f} TF/s")
+        row = {"load": f, "rate_req_s": lam, "serial": {k: serial[k] for k in keys}, "served": {}}
+        for budget in budgets:
+            served = run(arr, streams, 4 * streams, budget)
+            row["served"][str(budget >> 30) + "GiB"] = {k: served[k] for k in keys}
+            log(f"served load {f} budget {budget >> 30} GiB: p50 {served['p50_ms']:.2f} ms p99 "
+                f"{served['p99_ms']:.2f} ms {served['tflops']:.0f} TF/s | serial p50 {serial['p50_ms']:.2f} "
+                f"p99 {serial['p99_ms']:.2f} {serial['tflops']:.0f} TF/s")
+        res["rates"].append(row)
     return res
+
+
+def bench_ubench(lib, stream):
+    """Matrix-core and LDS microbenchmarks (the paper's Sec. 5 MFMA study on
+    gfx950): throughput against resident waves per CU, dependent-issue
+    latency, LDS read bandwidth."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    iters = 2000
+    out = {"cus": cus, "throughput": [], "latency": [], "lds": []}
+    for kind, (name, mnk) in lib.UBENCH_KINDS.items():
+        for waves in (1, 2, 4, 8, 16):
+            chains = 8 if kind in (0, 2) else 4
+            ms = lib.fp8_ubench_mfma(kind, waves, chains, iters, stream)
+            n_instr = cus * waves * chains * iters
+            out["throughput"].append({"instr": name, "waves_per_cu": waves, "chains": chains,
+                                      "tflops_dense_equiv": 2.0 * mnk * n_instr / (ms * 1e-3) / 1e12,
+                                      "ns_per_instr_per_wave": ms * 1e6 / (chains * iters)})
+        ms = lib.fp8_ubench_mfma(kind, 1, 1, iters, stream)
+        out["latency"].append({"instr": name, "ns_dependent_issue": ms * 1e6 / iters})
+    for waves in (1, 4, 8, 16):
+        ms = lib.fp8_ubench_lds(waves, 4096, stream)
+        nbytes = cus * waves * 64 * 16 * 4096
+        out["lds"].append({"waves_per_cu": waves, "tbs": nbytes / (ms * 1e-3) / 1e12})
+    return out
 
 
 def main():
@@ -457,9 +590,14 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the library's default plan")
     ap.add_argument("--sweep", action="store_true", help="also the square and skinny sweep with 2:4 break-even")
     ap.add_argument("--requests", type=int, default=20000, help="served stream length")
+    ap.add_argument("--served-sweep", action="store_true",
+                    help="served stream at 0.25..2.0 x serial capacity and 1, 2, 8 GiB budgets")
+    ap.add_argument("--ace-only", action="store_true", help="only the concurrent-stream study (for counter runs)")
+    ap.add_argument("--ubench-only", action="store_true", help="only the matrix-core and LDS microbenchmarks")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="only launch the headline GEMM 3 times and a 1 GiB device copy (for counter runs)")
+                    help="only launch the headline GEMM and its 2:4 form 3 times each and a 1 GiB device copy "
+                         "(for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the GEMM would shard by "
@@ -475,11 +613,19 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     M = N = K = args.size
+    if args.ace_only or args.ubench_only:
+        res = bench_ace(lib, stream) if args.ace_only else bench_ubench(lib, stream)
+        print(json.dumps({"ace" if args.ace_only else "ubench": res}), flush=True)
+        return
     if args.traffic_probe:
         xa, xb, qa, da, qb, db = make_operands(lib, M, N, K, 0)
         c = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
         for _ in range(3):
             lib.fp8_gemm(qa, qb, da, db, c=c, stream=stream)
+        # the 2:4 GEMM of the same shape (A pruned), on its default plan
+        va, ma, _ = lib.fp8_sparse24_prune_compress(qa, 0, with_mask=False, stream=stream)
+        for _ in range(3):
+            lib.fp8_sparse24_gemm(va, ma, qb, lib.FP8_SPARSE_A, da, db, c=c, stream=stream)
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -532,6 +678,7 @@ def main():
     qms = time_events(lambda: lib.fp8_quantize(xa, 0, lib.FP8_SCALE_ROW, stream=stream), 20, stream)
     extra["quantize_per_row"] = {"ms": qms, "gbs": M * K * 5 / qms / 1e6}
     extra["sparse24"] = bench_sparse(lib, qa, da, qb, db, max(5, args.steps // 2), 3, stream)
+    extra["ubench"] = bench_ubench(lib, stream)
     log(f"2:4: {extra['sparse24']['sparse_tflops_dense_equiv']:.1f} TFLOP/s dense-equivalent, "
         f"{extra['sparse24']['speedup_vs_dense']:.2f}x vs dense on the pruned matrix")
     del xa, xb, c
@@ -555,12 +702,14 @@ def main():
         torch.cuda.empty_cache()
         log("concurrent streams (512^3) ...")
         extra["ace"] = bench_ace(lib, stream)
-        for mode, r in extra["ace"]["modes"].items():
-            log(f"  {mode}: " + ", ".join(f"{x['streams']} streams {x['tflops']:.0f} TF/s x{x['speedup']:.2f}"
-                                          for x in r["rows"]))
         torch.cuda.empty_cache()
         log("served stream ...")
-        extra["served"] = bench_served(lib, n_requests=args.requests)
+        if args.served_sweep:
+            extra["served"] = bench_served(lib, n_requests=args.requests,
+                                           rates=(0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 2.0),
+                                           budgets=(1 << 30, 2 << 30, 8 << 30))
+        else:
+            extra["served"] = bench_served(lib, n_requests=args.requests)
         torch.cuda.empty_cache()
         # skinny shapes of the sweep (HBM-bound), B rotated past the caches
         extra["skinny"] = [bench_shape(lib, m, 8192, 8192, 0, stream, rotate=5) for m in (16, 64, 256)]
@@ -575,6 +724,10 @@ def main():
             sweep.append(bench_shape(lib, m, 8192, 8192, 1, stream, rotate=5))
         sweep.append(bench_shape(lib, 512, 2048, 1024, 0, stream))
         extra["sweep"] = sweep
+        # the dense-vs-2:4 records the library's tuner kept for these shapes
+        extra["breakeven_records"] = lib.fp8_tune_breakeven_records()
+        lib.fp8_tune_cache_save(os.path.join(ROOT, "gpurun_out", "tune_cache.jsonl")) if os.path.isdir(
+            os.path.join(ROOT, "gpurun_out")) else None
 
     out = {
         "metric": "FP8 TFLOP/s (% of peak) dense vs 2:4 sparse; grouped-serving p50/p99 latency",

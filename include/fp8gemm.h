@@ -109,10 +109,16 @@ typedef struct {
     int split_k;
 } fp8_plan;
 
-/* Describes compiled tile `tile`: macro-tile rows/cols, waves per workgroup
- * and whether it has a 2:4 kernel (*sparse = 0: a 2:4 plan naming it is
- * rejected with FP8_ERR_ARG).  Returns FP8_ERR_ARG past the last tile. */
-fp8_status fp8_tile_info(int tile, int *block_m, int *block_n, int *waves, int *sparse);
+/* Describes compiled tile `tile`: macro-tile rows/cols, waves per workgroup,
+ * whether it has a 2:4 kernel (*sparse) and a dense kernel (*dense) - a plan
+ * naming a tile without the kernel it needs is rejected with FP8_ERR_ARG -
+ * and whether it is an exact-sum tile (*exact: the FP8 codes are decoded to
+ * BF16 and summed on the BF16 MFMA, whose error stays inside the bound
+ * 4 K 2^-24 sum |a b| for every K; the FP8 MFMA tiles guarantee that bound
+ * only for K >= 3584, so plans the library chooses use exact-sum tiles below
+ * that K).  Any out pointer may be NULL.  FP8_ERR_ARG past the last tile. */
+fp8_status fp8_tile_info(int tile, int *block_m, int *block_n, int *waves, int *sparse, int *dense,
+                         int *exact);
 int fp8_num_tiles(void);
 
 /* The plan the library would use for these arguments (NULL plan = choose). */
@@ -181,19 +187,52 @@ fp8_status fp8_sparse24_gemm(const fp8_sparse24_gemm_args *args, const fp8_plan 
 /* Autotuner.                                                                */
 /* ------------------------------------------------------------------------ */
 /* Times every (tile, split_k) candidate for these arguments on `stream` with
- * HIP events (warmup, then iters timed launches, median taken), records the
- * best in the in-process tuning cache and returns it.  The caller's c buffer
- * is overwritten.  Workspace for the largest candidate is allocated by the
- * library for the duration of the call.  Keyed on (M bucket, N, K, formats,
- * output type, scale kinds, dense or sparse side). */
+ * HIP events (two warm-up calls, then iters timed calls, median taken),
+ * records the best in the in-process tuning cache and returns it.  The
+ * caller's c buffer is overwritten.  Workspace for the largest candidate is
+ * allocated by the library for the duration of the call.  Candidates are the
+ * exact-sum tiles when K < 3584 and the FP8 MFMA tiles otherwise (see
+ * fp8_tile_info).  Keyed on (M and N rounded up to powers of two, K,
+ * formats, output type, scale kinds, dense or sparse side). */
 fp8_status fp8_tune_gemm(const fp8_gemm_args *args, int iters, void *stream, fp8_plan *best,
                          double *best_us);
 fp8_status fp8_tune_sparse24_gemm(const fp8_sparse24_gemm_args *args, int iters, void *stream,
                                   fp8_plan *best, double *best_us);
-/* Persist / restore the tuning cache as JSON lines. */
+
+/* Dense versus 2:4 on one product (Sec. 7.1, where the 2:4 path is measured
+ * against dense on the same shapes to find where sparsity pays): both are
+ * tuned as above and the record {shape, side, formats, output type, best
+ * dense and 2:4 plans and times, use_sparse = 2:4 faster} is kept in the
+ * tuning cache.  `sparse` and `dense` must describe the same M, N, K,
+ * formats and output type; `dense` normally multiplies the decompressed
+ * (pruned) operand, so both compute the same result.  Lookups round M up to
+ * a power of two (N and K exact). */
+typedef struct {
+    int64_t M, N, K;
+    int side;                 /* fp8_sparse_side of the 2:4 operand */
+    int a_fmt, b_fmt, c_type;
+    double dense_us, sparse_us;
+    fp8_plan dense_plan, sparse_plan;
+    int use_sparse;
+} fp8_breakeven;
+fp8_status fp8_tune_sparse_vs_dense(const fp8_sparse24_gemm_args *sparse, const fp8_gemm_args *dense,
+                                    int iters, void *stream, fp8_breakeven *out);
+/* *found = 1 and *out filled when a record covers the shape, else *found = 0. */
+fp8_status fp8_tune_breakeven_lookup(int64_t M, int64_t N, int64_t K, fp8_sparse_side side, fp8_fmt a_fmt,
+                                     fp8_fmt b_fmt, fp8_out c_type, fp8_breakeven *out, int *found);
+int fp8_tune_breakeven_count(void);
+fp8_status fp8_tune_breakeven_get(int index, fp8_breakeven *out);
+
+/* Persist / restore the tuning cache (plans and dense-vs-2:4 records) as JSON
+ * lines.  Every line carries the device ("<architecture> <product name>") and
+ * HIP runtime version it was measured with; fp8_tune_cache_load skips lines
+ * of another device or runtime, and lines it cannot parse.
+ * fp8_tune_device_key gives the current device's identity ("none" and 0
+ * without a device; buf may be NULL). */
 fp8_status fp8_tune_cache_save(const char *path);
 fp8_status fp8_tune_cache_load(const char *path);
 void fp8_tune_cache_clear(void);
+fp8_status fp8_tune_device_key(char *buf, size_t bytes, int *runtime_version);
 
 /* ------------------------------------------------------------------------ */
 /* Grouped GEMM: many independent problems in one persistent launch.         */
@@ -221,6 +260,13 @@ fp8_status fp8_grouped_gemm(fp8_grouped_plan *plan, void *stream);
 fp8_status fp8_grouped_plan_info(const fp8_grouped_plan *plan, int *tile, int64_t *num_tiles,
                                  int *num_workgroups);
 fp8_status fp8_grouped_plan_destroy(fp8_grouped_plan *plan);
+/* Times one grouped launch of `problems` with each tile the grouped kernel is
+ * built for (plans created and destroyed inside; two warm-up launches, then
+ * iters timed launches, median) and returns the fastest tile and its time.
+ * The problems' outputs are overwritten.  Pass *best_tile to
+ * fp8_grouped_plan_create. */
+fp8_status fp8_grouped_tune(const fp8_group_problem *problems, int count, int iters, void *stream,
+                            int *best_tile, double *best_us);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: a continuous-batching request loop over several HIP streams.     */
@@ -302,6 +348,26 @@ fp8_status fp8_server_stats_get(fp8_server *srv, fp8_server_stats *stats);
 fp8_status fp8_server_reset_stats(fp8_server *srv);
 double fp8_server_now(fp8_server *srv);  /* seconds on the server clock */
 fp8_status fp8_server_destroy(fp8_server *srv);                               /* drains first */
+
+/* ------------------------------------------------------------------------ */
+/* Microbenchmarks of the matrix cores and the LDS.                          */
+/* ------------------------------------------------------------------------ */
+/* The counterpart of the paper's FP8 MFMA characterisation (Sec. 5): one
+ * workgroup per CU with waves_per_cu (1..16) wavefronts, each issuing
+ * `chains` (1, 4 or 8) independent accumulator chains of one instruction for
+ * `iters` rounds; *ms = device time of the launch.  kind: 0 = 16x16x128 FP8
+ * MFMA, 1 = 32x32x64 FP8 MFMA, 2 = 16x16x128 FP8 2:4 SMFMAC, 3 = 32x32x64 FP8
+ * SMFMAC.  With chains = 1 each instruction waits for the previous one
+ * (dependent-issue latency); with more chains and waves the issue rate
+ * (throughput).  A launch performs CUs x waves x 64 lanes worth of
+ * chains x iters instructions; FLOPs per instruction: 2 M N K of the dense
+ * shape (the SMFMAC counts the dense-equivalent 2 M N K).  Allocates a small
+ * sink buffer for the call.
+ * fp8_ubench_lds: waves_per_cu waves per CU each read 16 bytes per lane
+ * (ds_read_b128, conflict-free) `iters` times; bytes = CUs x waves x 64 x 16
+ * x iters. */
+fp8_status fp8_ubench_mfma(int kind, int waves_per_cu, int chains, int iters, void *stream, double *ms);
+fp8_status fp8_ubench_lds(int waves_per_cu, int iters, void *stream, double *ms);
 
 /* ------------------------------------------------------------------------ */
 /* Validator support: FP64 error norms on the device.                        */

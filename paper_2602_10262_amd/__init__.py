@@ -69,7 +69,7 @@ _SIGS = {
     "fp8_version": [],
     "fp8_quantize_workspace_size": [_I64, _I64, _I, _P],
     "fp8_quantize": [_P, _I64, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _SZ, _P],
-    "fp8_tile_info": [_I, _P, _P, _P, _P],
+    "fp8_tile_info": [_I, _P, _P, _P, _P, _P, _P],
     "fp8_num_tiles": [],
     "fp8_gemm_plan_resolve": [_P, _P, _P],
     "fp8_gemm_workspace_size": [_P, _P, _P],
@@ -85,6 +85,14 @@ _SIGS = {
     "fp8_tune_cache_save": [ctypes.c_char_p],
     "fp8_tune_cache_load": [ctypes.c_char_p],
     "fp8_tune_cache_clear": [],
+    "fp8_tune_sparse_vs_dense": [_P, _P, _I, _P, _P],
+    "fp8_tune_breakeven_lookup": [_I64, _I64, _I64, _I, _I, _I, _I, _P, _P],
+    "fp8_tune_breakeven_count": [],
+    "fp8_tune_breakeven_get": [_I, _P],
+    "fp8_tune_device_key": [_P, _SZ, _P],
+    "fp8_grouped_tune": [_P, _I, _I, _P, _P, _P],
+    "fp8_ubench_mfma": [_I, _I, _I, _I, _P, _P],
+    "fp8_ubench_lds": [_I, _I, _P, _P],
     "fp8_grouped_plan_create": [_P, _I, _I, _I, _P],
     "fp8_grouped_gemm": [_P, _P],
     "fp8_grouped_plan_info": [_P, _P, _P, _P],
@@ -104,7 +112,7 @@ _SIGS = {
     "fp8_validate": [_P, _I, _I64, _P, _P, _I64, _I64, _I64, _P, _P],
 }
 _RESTYPE = {"fp8_last_error": ctypes.c_char_p, "fp8_version": _I, "fp8_num_tiles": _I,
-            "fp8_noalloc_scratch_bytes": _SZ,
+            "fp8_noalloc_scratch_bytes": _SZ, "fp8_tune_breakeven_count": _I,
             "fp8_tune_cache_clear": None, "fp8_server_now": _D}
 
 _lib = None
@@ -254,9 +262,10 @@ def fp8_gemm_plan_resolve(args: GemmArgs, plan=None) -> tuple:
 
 
 def fp8_tile_info(tile: int) -> dict:
-    v = [ctypes.c_int(0) for _ in range(4)]
+    v = [ctypes.c_int(0) for _ in range(6)]
     _call("fp8_tile_info", tile, *[ctypes.byref(x) for x in v])
-    return {"block_m": v[0].value, "block_n": v[1].value, "waves": v[2].value, "sparse": v[3].value}
+    return {"block_m": v[0].value, "block_n": v[1].value, "waves": v[2].value, "sparse": v[3].value,
+            "dense": v[4].value, "exact": v[5].value}
 
 
 def fp8_num_tiles() -> int:
@@ -337,6 +346,52 @@ def fp8_tune_sparse24_gemm(args: Sparse24GemmArgs, iters: int = 10, stream=None)
     return (best.tile, best.split_k), us.value
 
 
+class Breakeven(ctypes.Structure):
+    _fields_ = [("M", _I64), ("N", _I64), ("K", _I64), ("side", _I), ("a_fmt", _I), ("b_fmt", _I), ("c_type", _I),
+                ("dense_us", _D), ("sparse_us", _D), ("dense_plan", Plan), ("sparse_plan", Plan),
+                ("use_sparse", _I)]
+
+    def as_dict(self) -> dict:
+        return {"M": self.M, "N": self.N, "K": self.K, "side": "A" if self.side == FP8_SPARSE_A else "B",
+                "a_fmt": self.a_fmt, "b_fmt": self.b_fmt, "c_type": self.c_type,
+                "dense_us": self.dense_us, "sparse_us": self.sparse_us,
+                "dense_plan": [self.dense_plan.tile, self.dense_plan.split_k],
+                "sparse_plan": [self.sparse_plan.tile, self.sparse_plan.split_k],
+                "use_sparse": bool(self.use_sparse), "speedup_2to4": self.dense_us / self.sparse_us}
+
+
+def fp8_tune_sparse_vs_dense(sparse_args: Sparse24GemmArgs, dense_args: GemmArgs, iters: int = 10,
+                             stream=None) -> dict:
+    r = Breakeven()
+    _call("fp8_tune_sparse_vs_dense", ctypes.byref(sparse_args), ctypes.byref(dense_args), iters, _stream(stream),
+          ctypes.byref(r))
+    return r.as_dict()
+
+
+def fp8_tune_breakeven_records() -> list:
+    L = load()
+    out = []
+    for i in range(L.fp8_tune_breakeven_count()):
+        r = Breakeven()
+        _call("fp8_tune_breakeven_get", i, ctypes.byref(r))
+        out.append(r.as_dict())
+    return out
+
+
+def fp8_tune_breakeven_lookup(M, N, K, side, a_fmt=FP8_E4M3, b_fmt=FP8_E4M3, c_type=FP8_OUT_BF16):
+    r = Breakeven()
+    found = ctypes.c_int(0)
+    _call("fp8_tune_breakeven_lookup", M, N, K, side, a_fmt, b_fmt, c_type, ctypes.byref(r), ctypes.byref(found))
+    return r.as_dict() if found.value else None
+
+
+def fp8_tune_device_key() -> tuple:
+    buf = ctypes.create_string_buffer(256)
+    rt = ctypes.c_int(0)
+    _call("fp8_tune_device_key", buf, 256, ctypes.byref(rt))
+    return buf.value.decode(), rt.value
+
+
 def fp8_tune_cache_save(path: str):
     _call("fp8_tune_cache_save", path.encode())
 
@@ -347,6 +402,25 @@ def fp8_tune_cache_load(path: str):
 
 def fp8_tune_cache_clear():
     load().fp8_tune_cache_clear()
+
+
+# ---------------------------------------------------------- microbenchmarks --
+
+UBENCH_KINDS = {0: ("mfma_16x16x128_f8", 16 * 16 * 128), 1: ("mfma_32x32x64_f8", 32 * 32 * 64),
+                2: ("smfmac_16x16x128_f8", 16 * 16 * 128), 3: ("smfmac_32x32x64_f8", 32 * 32 * 64)}
+
+
+def fp8_ubench_mfma(kind: int, waves_per_cu: int, chains: int, iters: int, stream=None) -> float:
+    """Device milliseconds of one microbenchmark launch (see the C header)."""
+    ms = ctypes.c_double(0)
+    _call("fp8_ubench_mfma", kind, waves_per_cu, chains, iters, _stream(stream), ctypes.byref(ms))
+    return ms.value
+
+
+def fp8_ubench_lds(waves_per_cu: int, iters: int, stream=None) -> float:
+    ms = ctypes.c_double(0)
+    _call("fp8_ubench_lds", waves_per_cu, iters, _stream(stream), ctypes.byref(ms))
+    return ms.value
 
 
 # -------------------------------------------------------------- validate ----
@@ -365,6 +439,16 @@ def fp8_validate(c, cref, sabs, K, stream=None) -> dict:
 
 
 # ----------------------------------------------------------------- grouped --
+
+def fp8_grouped_tune(problems, iters: int = 5, stream=None) -> tuple:
+    """(fastest grouped tile, its median microseconds) for these problems."""
+    arr = (GroupProblem * len(problems))(*problems)
+    t = ctypes.c_int(-1)
+    us = ctypes.c_double(0)
+    _call("fp8_grouped_tune", ctypes.cast(arr, _P), len(problems), iters, _stream(stream), ctypes.byref(t),
+          ctypes.byref(us))
+    return t.value, us.value
+
 
 class GroupedPlan:
     """Owns an fp8_grouped_plan; problems' buffers must outlive it."""

@@ -185,6 +185,8 @@ fp8_status resolve_plan(const Prepared &pr, const fp8_plan *plan, fp8_plan &res)
         if (plan->tile >= 0) {
             if (pr.sparse && !tile_desc(plan->tile).sparse_ok)
                 return set_error(FP8_ERR_ARG, "plan.tile has no 2:4 kernel");
+            if (!pr.sparse && !tile_desc(plan->tile).dense_ok)
+                return set_error(FP8_ERR_ARG, "plan.tile has no dense kernel");
             res.tile = plan->tile;
             const TileDesc &t = tile_desc(res.tile);
             res.split_k = default_splits(cdiv(pr.key.mk, t.bm) * cdiv(pr.key.nk, t.bn), pr.key.kk);
@@ -258,7 +260,7 @@ fp8_status fp8_quantize(const float *x, int64_t rows, int64_t cols, int64_t ldx,
     return FP8_OK;
 }
 
-fp8_status fp8_tile_info(int tile, int *block_m, int *block_n, int *waves, int *sparse)
+fp8_status fp8_tile_info(int tile, int *block_m, int *block_n, int *waves, int *sparse, int *dense, int *exact)
 {
     if (tile < 0 || tile >= num_tiles()) return set_error(FP8_ERR_ARG, "tile out of range");
     const TileDesc &t = tile_desc(tile);
@@ -266,6 +268,8 @@ fp8_status fp8_tile_info(int tile, int *block_m, int *block_n, int *waves, int *
     if (block_n) *block_n = t.bn;
     if (waves) *waves = t.waves;
     if (sparse) *sparse = t.sparse_ok;
+    if (dense) *dense = t.dense_ok;
+    if (exact) *exact = t.exact;
     return FP8_OK;
 }
 

@@ -6,8 +6,9 @@
 
 namespace fp8k {
 
-#define FP8_DESC(i, bm, bn, wm, wn, occ, pf) \
-    {bm, bn, wm * wn, (tile_sparse_ok(bm) || pf == kExactPF) ? 1 : 0, pf == kExactPF ? 1 : 0},
+#define FP8_DESC(i, bm, bn, wm, wn, occ, pf)                                                     \
+    {bm, bn, wm * wn, (tile_sparse_ok(bm) || pf == kExactPF) ? 1 : 0, pf == kExactPF ? 1 : 0, \
+     tile_dense_fits(bm, bn, pf) ? 1 : 0},
 static const TileDesc kTiles[] = {FP8_TILE_LIST(FP8_DESC)};
 #undef FP8_DESC
 

@@ -46,26 +46,30 @@ hipError_t launch_one(int fa, int fb, bool sp, const GemmParams &p, hipStream_t 
     const int nb = ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN);
     dim3 grid((unsigned)nb, 1, (unsigned)p.splits), block(WM * WN * 64);
 #define FP8_GO(FA, FB, SP) gemm_kernel<BM, BN, WM, WN, OCC, PF, FA, FB, SP, KFAST><<<grid, block, 0, st>>>(p)
-    if constexpr (tile_sparse_ok(BM) || PF == kExactPF) {
-        const int key = fa * 4 + fb * 2 + (sp ? 1 : 0);
-        switch (key) {
-        case 0: FP8_GO(0, 0, false); break;
-        case 1: FP8_GO(0, 0, true); break;
-        case 2: FP8_GO(0, 1, false); break;
-        case 3: FP8_GO(0, 1, true); break;
-        case 4: FP8_GO(1, 0, false); break;
-        case 5: FP8_GO(1, 0, true); break;
-        case 6: FP8_GO(1, 1, false); break;
-        default: FP8_GO(1, 1, true); break;
+    constexpr bool DENSE = tile_dense_fits(BM, BN, PF);
+    constexpr bool SPARSE = tile_sparse_ok(BM) || PF == kExactPF;
+    // (plan resolution rejects a dense or 2:4 request for a tile without that kernel)
+    if (sp) {
+        if constexpr (SPARSE) {
+            switch (fa * 2 + fb) {
+            case 0: FP8_GO(0, 0, true); break;
+            case 1: FP8_GO(0, 1, true); break;
+            case 2: FP8_GO(1, 0, true); break;
+            default: FP8_GO(1, 1, true); break;
+            }
+        } else {
+            return hipErrorInvalidValue;
         }
     } else {
-        // dense only (plan resolution rejects a 2:4 request for this tile)
-        if (sp) return hipErrorInvalidValue;
-        switch (fa * 2 + fb) {
-        case 0: FP8_GO(0, 0, false); break;
-        case 1: FP8_GO(0, 1, false); break;
-        case 2: FP8_GO(1, 0, false); break;
-        default: FP8_GO(1, 1, false); break;
+        if constexpr (DENSE) {
+            switch (fa * 2 + fb) {
+            case 0: FP8_GO(0, 0, false); break;
+            case 1: FP8_GO(0, 1, false); break;
+            case 2: FP8_GO(1, 0, false); break;
+            default: FP8_GO(1, 1, false); break;
+            }
+        } else {
+            return hipErrorInvalidValue;
         }
     }
 #undef FP8_GO

@@ -86,6 +86,8 @@ __device__ __forceinline__ void static_for(F &&f)
 // single round of loads (BM <= 32).
 constexpr bool tile_sparse_ok(int bm) { return bm % 64 == 0 || bm <= 32; }
 
+constexpr int kMaxLdsBytes = 160 * 1024;   // LDS of one CU (gfx950)
+
 // LDS of one tile: NSTAGE stages (2 for the register-prefetch loops, 3 for
 // the loop that also prefetches fragments, PF - 4 for the DMA loops).
 template <int BM, int BN, bool SP, int PF = 2>
@@ -100,6 +102,14 @@ struct TileSmem {
     static constexpr int NSTAGE = PF == 3 ? 3 : (EXACT ? 2 : (PF >= 6 ? PF - 4 : 2));
     static constexpr int TOTAL = NSTAGE * STAGE;
 };
+
+// Whether a tile's dense / 2:4 kernel fits in LDS (a three-stage 256 x 256
+// ring fits only with the compressed operand: 3 x 52 KiB).
+constexpr bool tile_dense_fits(int bm, int bn, int pf)
+{
+    return (pf == 3 ? 3 : (pf == kExactPF ? 2 : (pf >= 6 ? pf - 4 : 2))) *
+               ((pf == kExactPF ? 256 : 128) * (bm + bn)) <= kMaxLdsBytes;
+}
 
 // Compressed rows (64 value bytes) keep their 16-byte chunk c at c ^ h(r),
 // h(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1): the 16 rows a fragment read touches

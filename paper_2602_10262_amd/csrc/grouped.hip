@@ -252,4 +252,57 @@ fp8_status fp8_grouped_plan_destroy(fp8_grouped_plan *plan)
     return FP8_OK;
 }
 
+fp8_status fp8_grouped_tune(const fp8_group_problem *problems, int count, int iters, void *stream, int *best_tile,
+                            double *best_us)
+{
+    if (!best_tile) return set_error(FP8_ERR_ARG, "null best_tile");
+    if (iters < 1) iters = 1;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    static const int kTiles[] = {
+#define FP8_GT(i) i,
+        FP8_GROUP_TILES(FP8_GT)
+#undef FP8_GT
+    };
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return set_error(FP8_ERR_HIP, "event creation failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_error(FP8_ERR_HIP, "event creation failed");
+    }
+    double best = 1e30;
+    int bt = -1;
+    fp8_status status = FP8_OK;
+    for (int tile : kTiles) {
+        fp8_grouped_plan *plan = nullptr;
+        status = fp8_grouped_plan_create(problems, count, tile, 0, &plan);
+        if (status != FP8_OK) break;
+        std::vector<float> times;
+        for (int i = 0; i < iters + 2 && status == FP8_OK; ++i) {
+            (void)hipEventRecord(e0, st);
+            status = fp8_grouped_gemm(plan, st);
+            (void)hipEventRecord(e1, st);
+            if (status != FP8_OK) break;
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (i >= 2) times.push_back(ms);
+        }
+        (void)hipStreamSynchronize(st);
+        fp8_grouped_plan_destroy(plan);
+        if (status != FP8_OK) break;
+        std::nth_element(times.begin(), times.begin() + times.size() / 2, times.end());
+        const double us = 1000.0 * times[times.size() / 2];
+        if (us < best) {
+            best = us;
+            bt = tile;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != FP8_OK) return status;
+    *best_tile = bt;
+    if (best_us) *best_us = best;
+    return FP8_OK;
+}
+
 }  // extern "C"

@@ -31,7 +31,8 @@ struct GemmParams {
 
 struct TileDesc {
     int bm, bn, waves, sparse_ok;
-    int exact;   // FP8 decoded to BF16 and summed on the BF16 MFMA (bound holds for every K)
+    int exact;     // FP8 decoded to BF16 and summed on the BF16 MFMA (bound holds for every K)
+    int dense_ok;  // has a dense kernel (a 2:4-only tile's dense stages would not fit in LDS)
 };
 
 // Below this K the FP8 MFMA's in-instruction truncation is not guaranteed to

@@ -76,19 +76,38 @@ def test_gpu_tests_cover_every_tile():
 
 
 def test_tuning_cache_roundtrip(tmp_path):
-    L = lib.load()
+    """Plans and dense-vs-2:4 records persist as JSON lines keyed by the
+    device and runtime they were measured on; other devices' lines are
+    skipped on load."""
+    import json
     lib.fp8_tune_cache_clear()
+    dev, rt = lib.fp8_tune_device_key()
+    plan = {"kind": "plan", "device": dev, "runtime": rt, "mk": 8192, "nk": 8192, "kk": 8192, "fa": 0, "fb": 0,
+            "out_bf16": 1, "si_per": 1, "sj_per": 1, "sparse": 0, "tile": 3, "split_k": 2, "us": 123.0}
+    be = {"kind": "breakeven", "device": dev, "runtime": rt, "M": 16, "N": 8192, "K": 8192, "side": 1, "fa": 0,
+          "fb": 0, "c_type": 1, "dense_us": 20.0, "sparse_us": 15.0, "dense_tile": 24, "dense_split": 1,
+          "sparse_tile": 4, "sparse_split": 4, "use_sparse": 1}
+    other = dict(plan, device="gfx000 elsewhere", tile=5)
     p = tmp_path / "cache.jsonl"
-    p.write_text('{"mk": 8192, "nk": 8192, "kk": 8192, "fa": 0, "fb": 0, "out_bf16": 1, "si_per": 1, '
-                 '"sj_per": 1, "sparse": 0, "tile": 3, "split_k": 2, "us": 123.000}\n')
+    p.write_text("\n".join(json.dumps(x) for x in (other, plan, be)) + "\n")
     lib.fp8_tune_cache_load(str(p))
     args = lib.GemmArgs(8192, 8192, 8192, 4096, 0, 8192, 4096, 0, 8192, 256, 1, 256, 1, 256, 1, 8192)
     assert lib.fp8_gemm_plan_resolve(args) == (3, 2)
+    rec = lib.fp8_tune_breakeven_lookup(9, 8192, 8192, lib.FP8_SPARSE_B)   # M rounds up to 16
+    assert rec and rec["use_sparse"] and rec["sparse_plan"] == [4, 4] and rec["speedup_2to4"] == 20.0 / 15.0
+    assert lib.fp8_tune_breakeven_lookup(9, 8192, 8192, lib.FP8_SPARSE_A) is None
     out = tmp_path / "out.jsonl"
     lib.fp8_tune_cache_save(str(out))
-    assert '"tile": 3' in out.read_text()
+    lines = [json.loads(x) for x in out.read_text().splitlines()]
+    assert {x["kind"] for x in lines} == {"plan", "breakeven"}
+    assert all(x["device"] == dev and x["runtime"] == rt for x in lines)
+    assert not any(x.get("tile") == 5 for x in lines)
     lib.fp8_tune_cache_clear()
     assert lib.fp8_gemm_plan_resolve(args) != (3, 2)
+    assert lib.fp8_tune_breakeven_records() == []
+    lib.fp8_tune_cache_load(str(out))
+    assert lib.fp8_gemm_plan_resolve(args) == (3, 2) and len(lib.fp8_tune_breakeven_records()) == 1
+    lib.fp8_tune_cache_clear()
 
 
 def test_noalloc_entry_point_without_gpu():
