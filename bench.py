@@ -316,6 +316,19 @@ def bench_sparse(lib, qa, da, qb, db, iters, warmup, stream):
     for _ in range(warmup):
         fnd()
     ms_dense_pruned = time_events(fnd, iters, stream)
+    # both sides pruned: the weight rows too; dense on the two pruned matrices
+    vw, mw, _ = lib.fp8_sparse24_prune_compress(qb, 0, with_mask=False)
+    pruned_w = lib.fp8_sparse24_decompress(vw, mw, K)
+    fnb = lambda: lib.fp8_sparse24_both_gemm(values, meta, vw, mw, da, db, c=c, stream=stream)
+    for _ in range(warmup):
+        fnb()
+    ms_both = time_events(fnb, iters, stream)
+    fnbd = lambda: lib.fp8_gemm(pruned, pruned_w, da, db, c=cd, stream=stream)
+    for _ in range(warmup):
+        fnbd()
+    ms_both_dense = time_events(fnbd, iters, stream)
+    both_plan = lib.fp8_sparse24_both_gemm_plan_resolve(
+        lib.sparse24_both_args(values, meta, vw, mw, da, db, c))
     flops = 2.0 * M * N * K
     return {
         "shape": [M, N, K],
@@ -323,7 +336,37 @@ def bench_sparse(lib, qa, da, qb, db, iters, warmup, stream):
         "sparse_frac_of_2to4_peak": flops / ms / 1e9 / PEAK_FP8_SPARSE_TFLOPS,
         "dense_on_pruned_ms": ms_dense_pruned, "speedup_vs_dense": ms_dense_pruned / ms,
         "prune_compress_ms": prune_ms, "prune_gbs": (M * K * (1 + 0.5 + 0.125)) / prune_ms / 1e6,
+        "both_sides": {"ms": ms_both, "plan": list(both_plan), "tflops_dense_equiv": flops / ms_both / 1e9,
+                       "dense_on_both_pruned_ms": ms_both_dense, "speedup_vs_dense": ms_both_dense / ms_both},
     }
+
+
+def bench_encode(lib, stream, sizes=(256, 512, 2048, 8192)):
+    """The 2:4 encode step (the overhead the paper measures apart from the
+    GEMM): FP32 -> codes -> pruned and compressed, per-row scales, as two
+    launches (quantize, then prune) and as the fused pass; one side and both
+    sides (two operands of the same size)."""
+    import torch
+    out = []
+    for S in sizes:
+        g = torch.Generator(device="cuda").manual_seed(S)
+        x = torch.randn((S, S), dtype=torch.float32, device="cuda", generator=g)
+        q, _, _ = lib.fp8_quantize(x, 0, lib.FP8_SCALE_ROW, stream=stream)
+        # one untimed call of each kernel first (the first launch loads the code)
+        lib.fp8_sparse24_prune_compress(q, 0, with_mask=False, stream=stream)
+        lib.fp8_quantize_prune24(x, 0, lib.FP8_SCALE_ROW, with_mask=False, stream=stream)
+        n = 50 if S <= 2048 else 20
+        t_q = time_events(lambda: lib.fp8_quantize(x, 0, lib.FP8_SCALE_ROW, stream=stream), n, stream)
+        t_p = time_events(lambda: lib.fp8_sparse24_prune_compress(q, 0, with_mask=False, stream=stream), n, stream)
+        t_f = time_events(lambda: lib.fp8_quantize_prune24(x, 0, lib.FP8_SCALE_ROW, with_mask=False, stream=stream),
+                          n, stream)
+        elems = S * S
+        out.append({"rows": S, "K": S, "quantize_us": t_q * 1e3, "prune_us": t_p * 1e3,
+                    "quantize_then_prune_us": (t_q + t_p) * 1e3, "fused_us": t_f * 1e3,
+                    "fused_gbs": elems * (4 + 0.5 + 0.125) / t_f / 1e6,
+                    "both_sides_fused_us": 2 * t_f * 1e3})
+        del x, q
+    return out
 
 
 def bench_shape(lib, M, N, K, fa, stream, iters=20, tune=True, rotate=1, sparse_too=True):
@@ -576,6 +619,14 @@ def bench_ubench(lib, stream):
         ms = lib.fp8_ubench_lds(waves, 4096, stream)
         nbytes = cus * waves * 64 * 16 * 4096
         out["lds"].append({"waves_per_cu": waves, "tbs": nbytes / (ms * 1e-3) / 1e12})
+    # the address patterns of the GEMM fragment reads, 8 waves per CU
+    out["lds_patterns"] = []
+    for pat, name in lib.LDS_PATTERNS.items():
+        ms = lib.fp8_ubench_lds_pattern(pat, 8, 4096, stream)
+        per_lane = 4 if pat == 4 else 16
+        nbytes = cus * 8 * 64 * per_lane * 4096
+        out["lds_patterns"].append({"pattern": name, "tbs": nbytes / (ms * 1e-3) / 1e12,
+                                    "ns_per_instr_per_wave": ms * 1e6 / 4096})
     return out
 
 
@@ -679,6 +730,7 @@ def main():
     extra["quantize_per_row"] = {"ms": qms, "gbs": M * K * 5 / qms / 1e6}
     extra["sparse24"] = bench_sparse(lib, qa, da, qb, db, max(5, args.steps // 2), 3, stream)
     extra["ubench"] = bench_ubench(lib, stream)
+    extra["encode"] = bench_encode(lib, stream)
     log(f"2:4: {extra['sparse24']['sparse_tflops_dense_equiv']:.1f} TFLOP/s dense-equivalent, "
         f"{extra['sparse24']['speedup_vs_dense']:.2f}x vs dense on the pruned matrix")
     del xa, xb, c

@@ -160,6 +160,21 @@ fp8_status fp8_gemm_noalloc(const fp8_gemm_args *args, const fp8_plan *plan, voi
 fp8_status fp8_sparse24_prune_compress(const uint8_t *x, fp8_fmt fmt, int64_t rows, int64_t K,
                                        int64_t ldx, uint8_t *values, uint8_t *meta, uint8_t *mask,
                                        void *stream);
+/* Quantize and prune in one pass (the encode step of the 2:4 path, Sec. 7.1.1,
+ * whose cost the method measures separately from the GEMM): the FP32 rows x K
+ * matrix x is quantized exactly as fp8_quantize does (same amax, scale and
+ * codes, per tensor or per row) and the codes are pruned and compressed
+ * exactly as fp8_sparse24_prune_compress does, without the dense codes ever
+ * being written.  Outputs: values, meta, mask (may be NULL) in the layout
+ * above; scale and descale (1 or rows floats).  ws: fp8_quantize_workspace_size
+ * (rows, K, kind) bytes (4 for TENSOR, none for ROW).  Requirements: K % 8 ==
+ * 0, x 16-byte aligned with ldx % 4 == 0, values/meta/mask 16-byte aligned.
+ * Errors: FP8_ERR_ARG (null pointer, bad enum, ldx < K, workspace),
+ * FP8_ERR_SHAPE, FP8_ERR_ALIGN; nothing is enqueued on error. */
+fp8_status fp8_quantize_prune24(const float *x, int64_t rows, int64_t K, int64_t ldx, fp8_fmt fmt,
+                                fp8_scale_kind kind, uint8_t *values, uint8_t *meta, uint8_t *mask,
+                                float *scale, float *descale, void *ws, size_t ws_bytes, void *stream);
+
 /* The pruned dense matrix: out[r*ldo + k] = survivor code or +0 (0x00). */
 fp8_status fp8_sparse24_decompress(const uint8_t *values, const uint8_t *meta, int64_t rows,
                                    int64_t K, uint8_t *out, int64_t ldo, void *stream);
@@ -182,6 +197,31 @@ fp8_status fp8_sparse24_gemm_workspace_size(const fp8_sparse24_gemm_args *args, 
                                             size_t *bytes);
 fp8_status fp8_sparse24_gemm(const fp8_sparse24_gemm_args *args, const fp8_plan *plan, void *ws,
                              size_t ws_bytes, void *stream);
+
+/* Both operands 2:4-compressed (the both-side sparsity pattern, Sec. 7.1):
+ * C = A' x W'^T, where A' (M x K activations) and W' (N x K weight rows) are
+ * the pruned matrices given in the compressed form above, i.e. the sum runs
+ * over the k that both operands keep.  g.a and g.b are unused; formats,
+ * scales and output as in fp8_gemm.  No instruction takes two compressed
+ * operands: one operand feeds the 2:4 MFMA and the other is expanded to its
+ * dense rows inside the kernel (never in memory), so it is read from HBM at
+ * 0.625 bytes per element.  Plans: tiles 0, 3, 11, 12 (FP8 MFMA) and the
+ * exact-sum tiles 25, 26 (chosen for K < 3584, as for the other GEMMs); any
+ * other tile is rejected with FP8_ERR_ARG.  Requirements: K % 8 == 0 and the
+ * four compressed pointers 16-byte aligned.  The result equals fp8_gemm on
+ * the two decompressed operands up to FP32 summation order. */
+typedef struct {
+    fp8_gemm_args g;
+    const uint8_t *a_values, *a_meta;   /* compressed M x K activations */
+    const uint8_t *b_values, *b_meta;   /* compressed N x K weight rows */
+} fp8_sparse24_both_gemm_args;
+
+fp8_status fp8_sparse24_both_gemm_plan_resolve(const fp8_sparse24_both_gemm_args *args, const fp8_plan *plan,
+                                               fp8_plan *resolved);
+fp8_status fp8_sparse24_both_gemm_workspace_size(const fp8_sparse24_both_gemm_args *args, const fp8_plan *plan,
+                                                 size_t *bytes);
+fp8_status fp8_sparse24_both_gemm(const fp8_sparse24_both_gemm_args *args, const fp8_plan *plan, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Autotuner.                                                                */
@@ -365,9 +405,19 @@ fp8_status fp8_server_destroy(fp8_server *srv);                               /*
  * sink buffer for the call.
  * fp8_ubench_lds: waves_per_cu waves per CU each read 16 bytes per lane
  * (ds_read_b128, conflict-free) `iters` times; bytes = CUs x waves x 64 x 16
- * x iters. */
+ * x iters.
+ * fp8_ubench_lds_pattern: the same with the address pattern of a GEMM
+ * fragment read (lane l reads row l % 16 of a 16-row block at chunk position
+ * l / 16; each iteration moves to the next block): 0 linear (= fp8_ubench_lds),
+ * 1 dense operand (128-byte swizzled rows, 16 bytes at chunk 2 (l/16)),
+ * 2 compressed operand (64-byte swizzled rows), 3 dense operand at the 2:4 B
+ * chunk positions, 4 metadata (16-byte rows, 4 bytes per lane: ds_read_b32),
+ * 5 compressed operand without swizzle.  Bank conflicts of a pattern appear
+ * as a longer time (and in the LDS conflict counters).  Patterns outside 0..5
+ * are rejected with FP8_ERR_ARG. */
 fp8_status fp8_ubench_mfma(int kind, int waves_per_cu, int chains, int iters, void *stream, double *ms);
 fp8_status fp8_ubench_lds(int waves_per_cu, int iters, void *stream, double *ms);
+fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void *stream, double *ms);
 
 /* ------------------------------------------------------------------------ */
 /* Validator support: FP64 error norms on the device.                        */

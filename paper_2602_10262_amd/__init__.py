@@ -42,6 +42,10 @@ class Sparse24GemmArgs(ctypes.Structure):
     _fields_ = [("g", GemmArgs), ("side", _I), ("values", _P), ("meta", _P)]
 
 
+class Sparse24BothGemmArgs(ctypes.Structure):
+    _fields_ = [("g", GemmArgs), ("a_values", _P), ("a_meta", _P), ("b_values", _P), ("b_meta", _P)]
+
+
 class GroupProblem(ctypes.Structure):
     _fields_ = [("is_sparse", _I), ("dense", GemmArgs), ("sparse", Sparse24GemmArgs)]
 
@@ -78,6 +82,7 @@ _SIGS = {
     "fp8_noalloc_scratch_bytes": [],
     "fp8_sparse24_prune_compress": [_P, _I, _I64, _I64, _I64, _P, _P, _P, _P],
     "fp8_sparse24_decompress": [_P, _P, _I64, _I64, _P, _I64, _P],
+    "fp8_quantize_prune24": [_P, _I64, _I64, _I64, _I, _I, _P, _P, _P, _P, _P, _P, _SZ, _P],
     "fp8_sparse24_gemm_workspace_size": [_P, _P, _P],
     "fp8_sparse24_gemm": [_P, _P, _P, _SZ, _P],
     "fp8_tune_gemm": [_P, _I, _P, _P, _P],
@@ -93,6 +98,10 @@ _SIGS = {
     "fp8_grouped_tune": [_P, _I, _I, _P, _P, _P],
     "fp8_ubench_mfma": [_I, _I, _I, _I, _P, _P],
     "fp8_ubench_lds": [_I, _I, _P, _P],
+    "fp8_ubench_lds_pattern": [_I, _I, _I, _P, _P],
+    "fp8_sparse24_both_gemm_plan_resolve": [_P, _P, _P],
+    "fp8_sparse24_both_gemm_workspace_size": [_P, _P, _P],
+    "fp8_sparse24_both_gemm": [_P, _P, _P, _SZ, _P],
     "fp8_grouped_plan_create": [_P, _I, _I, _I, _P],
     "fp8_grouped_gemm": [_P, _P],
     "fp8_grouped_plan_info": [_P, _P, _P, _P],
@@ -286,6 +295,24 @@ def fp8_sparse24_prune_compress(x, fmt=FP8_E4M3, with_mask=True, stream=None):
     return values, meta, mask
 
 
+def fp8_quantize_prune24(x, fmt=FP8_E4M3, kind=FP8_SCALE_ROW, with_mask=True, ws=None, stream=None):
+    """FP32 rows x K (CUDA tensor, row-major) -> (values, meta, mask or None, s, d) in one pass."""
+    import torch
+    rows, K = x.shape
+    n = rows if kind == FP8_SCALE_ROW else 1
+    values = torch.empty((rows, K // 2), dtype=torch.uint8, device=x.device)
+    meta = torch.empty((rows, K // 8), dtype=torch.uint8, device=x.device)
+    mask = torch.empty((rows, K // 8), dtype=torch.uint8, device=x.device) if with_mask else None
+    scale = torch.empty(n, dtype=torch.float32, device=x.device)
+    descale = torch.empty(n, dtype=torch.float32, device=x.device)
+    if ws is None and kind == FP8_SCALE_TENSOR:
+        ws = torch.empty(16, dtype=torch.uint8, device=x.device)
+    _call("fp8_quantize_prune24", x.data_ptr(), rows, K, x.stride(0), fmt, kind, values.data_ptr(), meta.data_ptr(),
+          _ptr(mask), scale.data_ptr(), descale.data_ptr(), _ptr(ws),
+          0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+    return values, meta, mask, scale, descale
+
+
 def fp8_sparse24_decompress(values, meta, K, out=None, stream=None):
     import torch
     rows = values.shape[0]
@@ -327,6 +354,37 @@ def fp8_sparse24_gemm(values, meta, dense, side, a_descale, b_descale, sparse_fm
         nbytes = ws.numel() * ws.element_size()
     _call("fp8_sparse24_gemm", ctypes.byref(args), pref, _ptr(ws), nbytes, _stream(stream))
     return c
+
+
+def sparse24_both_args(a_values, a_meta, b_values, b_meta, a_descale, b_descale, c, a_fmt=FP8_E4M3,
+                       b_fmt=FP8_E4M3):
+    M, N, K = a_values.shape[0], b_values.shape[0], a_values.shape[1] * 2
+    g = gemm_args(None, None, a_descale, b_descale, c, a_fmt, b_fmt, M=M, N=N, K=K)
+    return Sparse24BothGemmArgs(g, a_values.data_ptr(), a_meta.data_ptr(), b_values.data_ptr(), b_meta.data_ptr())
+
+
+def fp8_sparse24_both_gemm(a_values, a_meta, b_values, b_meta, a_descale, b_descale, a_fmt=FP8_E4M3,
+                           b_fmt=FP8_E4M3, out_dtype=None, c=None, plan=None, ws=None, stream=None):
+    """C = A' x W'^T with both operands given compressed: (a_values, a_meta) the
+    M x K activations, (b_values, b_meta) the N x K weight rows."""
+    import torch
+    M, N = a_values.shape[0], b_values.shape[0]
+    if c is None:
+        c = torch.empty((M, N), dtype=out_dtype or torch.float32, device=a_values.device)
+    args = sparse24_both_args(a_values, a_meta, b_values, b_meta, a_descale, b_descale, c, a_fmt, b_fmt)
+    pref = _plan(plan)
+    if ws is None:
+        ws, nbytes = _workspace("fp8_sparse24_both_gemm_workspace_size", ctypes.byref(args), pref, a_values.device)
+    else:
+        nbytes = ws.numel() * ws.element_size()
+    _call("fp8_sparse24_both_gemm", ctypes.byref(args), pref, _ptr(ws), nbytes, _stream(stream))
+    return c
+
+
+def fp8_sparse24_both_gemm_plan_resolve(args, plan=None):
+    res = Plan(0, 0)
+    _call("fp8_sparse24_both_gemm_plan_resolve", ctypes.byref(args), _plan(plan), ctypes.byref(res))
+    return res.tile, res.split_k
 
 
 # ----------------------------------------------------------------- tuning ---
@@ -420,6 +478,16 @@ def fp8_ubench_mfma(kind: int, waves_per_cu: int, chains: int, iters: int, strea
 def fp8_ubench_lds(waves_per_cu: int, iters: int, stream=None) -> float:
     ms = ctypes.c_double(0)
     _call("fp8_ubench_lds", waves_per_cu, iters, _stream(stream), ctypes.byref(ms))
+    return ms.value
+
+
+LDS_PATTERNS = {0: "linear", 1: "dense_fragment", 2: "compressed_fragment", 3: "dense_at_2to4_b_chunks",
+                4: "metadata_b32", 5: "compressed_unswizzled"}
+
+
+def fp8_ubench_lds_pattern(pattern: int, waves_per_cu: int, iters: int, stream=None) -> float:
+    ms = ctypes.c_double(0)
+    _call("fp8_ubench_lds_pattern", pattern, waves_per_cu, iters, _stream(stream), ctypes.byref(ms))
     return ms.value
 
 

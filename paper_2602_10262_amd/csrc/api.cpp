@@ -323,6 +323,26 @@ fp8_status fp8_sparse24_prune_compress(const uint8_t *x, fp8_fmt fmt, int64_t ro
     return FP8_OK;
 }
 
+fp8_status fp8_quantize_prune24(const float *x, int64_t rows, int64_t K, int64_t ldx, fp8_fmt fmt,
+                                fp8_scale_kind kind, uint8_t *values, uint8_t *meta, uint8_t *mask, float *scale,
+                                float *descale, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!x || !values || !meta || !scale || !descale) return set_error(FP8_ERR_ARG, "null pointer");
+    if (rows < 1 || K < 1 || rows > kMaxDim || K > kMaxDim) return set_error(FP8_ERR_SHAPE, "rows, K out of range");
+    if (K % 8) return set_error(FP8_ERR_SHAPE, "K % 8 != 0");
+    if (!fmt_ok(fmt)) return set_error(FP8_ERR_ARG, "unknown FP8 format");
+    if (kind != FP8_SCALE_TENSOR && kind != FP8_SCALE_ROW) return set_error(FP8_ERR_ARG, "unknown scale kind");
+    if (ldx < K) return set_error(FP8_ERR_ARG, "ldx < K");
+    if (!aligned16(x) || ldx % 4) return set_error(FP8_ERR_ALIGN, "x must be 16-byte aligned with ldx % 4 == 0");
+    if (!aligned16(values) || !aligned16(meta) || (mask && !aligned16(mask)))
+        return set_error(FP8_ERR_ALIGN, "values, meta and mask must be 16-byte aligned");
+    if (kind == FP8_SCALE_TENSOR && (!ws || ws_bytes < 4)) return set_error(FP8_ERR_ARG, "workspace too small: need 4");
+    hipError_t e = launch_quantize_prune24(x, rows, K, ldx, fmt, kind == FP8_SCALE_ROW, values, meta, mask, scale,
+                                           descale, ws, as_stream(stream));
+    if (e != hipSuccess) return hip_error(e, "quantize+prune launch");
+    return FP8_OK;
+}
+
 fp8_status fp8_sparse24_decompress(const uint8_t *values, const uint8_t *meta, int64_t rows, int64_t K, uint8_t *out,
                                    int64_t ldo, void *stream)
 {
@@ -358,6 +378,120 @@ fp8_status fp8_sparse24_gemm(const fp8_sparse24_gemm_args *args, const fp8_plan 
     st = resolve_plan(pr, plan, res);
     if (st != FP8_OK) return st;
     return run_prepared(pr, res, ws, ws_bytes, as_stream(stream));
+}
+
+// ---- both operands 2:4-compressed ----------------------------------------
+
+// Kernel view: the compressed activations take the SMFMAC slot (i = rows of
+// A) unless A has fewer than 64 rows and the weight at least 64, in which case
+// the weight rows do and the output is stored transposed, as in the
+// weight-side 2:4 GEMM.
+static fp8_status prepare_both(const fp8_sparse24_both_gemm_args *s, Prepared &out)
+{
+    if (!s) return set_error(FP8_ERR_ARG, "null args");
+    const fp8_gemm_args *a = &s->g;
+    fp8_status st = check_common(a, false, false);
+    if (st != FP8_OK) return st;
+    if (a->K % 8) return set_error(FP8_ERR_SHAPE, "2:4 GEMM needs K % 8 == 0");
+    if (!s->a_values || !s->a_meta || !s->b_values || !s->b_meta)
+        return set_error(FP8_ERR_ARG, "null compressed operand");
+    if (!aligned16(s->a_values) || !aligned16(s->a_meta) || !aligned16(s->b_values) || !aligned16(s->b_meta))
+        return set_error(FP8_ERR_ALIGN, "compressed values and metadata must be 16-byte aligned");
+    const bool swap = a->M < 64 && a->N >= 64;
+    GemmParams &p = out.p;
+    std::memset(&p, 0, sizeof(p));
+    p.lda = p.ldb = a->K / 2;
+    p.ldm = p.ldmb = a->K / 8;
+    p.c = a->c; p.ldc = a->ldc; p.out_bf16 = a->c_type == FP8_OUT_BF16;
+    p.K = (int)a->K;
+    p.splits = 1; p.kchunk = ((p.K + kBKHost - 1) / kBKHost) * kBKHost;
+    if (!swap) {
+        p.a = s->a_values; p.meta = s->a_meta;
+        p.b = s->b_values; p.meta_b = s->b_meta;
+        p.si = a->a_descale; p.si_per = a->a_kind == FP8_SCALE_ROW;
+        p.sj = a->b_descale; p.sj_per = a->b_kind == FP8_SCALE_ROW;
+        p.M = (int)a->M; p.N = (int)a->N; p.trans_out = 0;
+        out.fa = a->a_fmt; out.fb = a->b_fmt;
+    } else {
+        p.a = s->b_values; p.meta = s->b_meta;
+        p.b = s->a_values; p.meta_b = s->a_meta;
+        p.si = a->b_descale; p.si_per = a->b_kind == FP8_SCALE_ROW;
+        p.sj = a->a_descale; p.sj_per = a->a_kind == FP8_SCALE_ROW;
+        p.M = (int)a->N; p.N = (int)a->M; p.trans_out = 1;
+        out.fa = a->b_fmt; out.fb = a->a_fmt;
+    }
+    out.sparse = true;
+    out.key = GemmKey{p.M, p.N, a->K, out.fa, out.fb, p.out_bf16, p.si_per, p.sj_per, 3};
+    return FP8_OK;
+}
+
+static fp8_status resolve_both(const Prepared &pr, const fp8_plan *plan, fp8_plan &res)
+{
+    const int64_t M = pr.p.M, N = pr.p.N, K = pr.p.K;
+    if (K < kExactBelowK) res.tile = cdiv(M, 128) * cdiv(N, 128) >= 256 ? 25 : 26;
+    else if (M >= 4096 && N >= 4096) res.tile = 12;
+    else if (M <= 64 || N <= 64) res.tile = 3;
+    else res.tile = 0;
+    if (plan && plan->tile >= 0) {
+        if (!both_tile_supported(plan->tile)) return set_error(FP8_ERR_ARG, "plan.tile has no both-sides 2:4 kernel");
+        res.tile = plan->tile;
+    }
+    const TileDesc &t = tile_desc(res.tile);
+    res.split_k = default_splits(cdiv(M, t.bm) * cdiv(N, t.bn), K);
+    if (plan && plan->split_k > 0) res.split_k = plan->split_k;
+    GemmParams p = pr.p;
+    apply_split(p, res.split_k);
+    res.split_k = p.splits;
+    return FP8_OK;
+}
+
+fp8_status fp8_sparse24_both_gemm_workspace_size(const fp8_sparse24_both_gemm_args *args, const fp8_plan *plan,
+                                                 size_t *bytes)
+{
+    if (!bytes) return set_error(FP8_ERR_ARG, "null bytes");
+    Prepared pr;
+    fp8_status st = prepare_both(args, pr);
+    if (st != FP8_OK) return st;
+    fp8_plan res;
+    st = resolve_both(pr, plan, res);
+    if (st != FP8_OK) return st;
+    *bytes = workspace_bytes(pr, res);
+    return FP8_OK;
+}
+
+fp8_status fp8_sparse24_both_gemm_plan_resolve(const fp8_sparse24_both_gemm_args *args, const fp8_plan *plan,
+                                               fp8_plan *resolved)
+{
+    if (!resolved) return set_error(FP8_ERR_ARG, "null resolved");
+    Prepared pr;
+    fp8_status st = prepare_both(args, pr);
+    if (st != FP8_OK) return st;
+    return resolve_both(pr, plan, *resolved);
+}
+
+fp8_status fp8_sparse24_both_gemm(const fp8_sparse24_both_gemm_args *args, const fp8_plan *plan, void *ws,
+                                  size_t ws_bytes, void *stream)
+{
+    Prepared pr;
+    fp8_status st = prepare_both(args, pr);
+    if (st != FP8_OK) return st;
+    fp8_plan res;
+    st = resolve_both(pr, plan, res);
+    if (st != FP8_OK) return st;
+    apply_split(pr.p, res.split_k);
+    const size_t need = workspace_bytes(pr, res);
+    if (need > 0) {
+        if (!ws || ws_bytes < need) return set_error(FP8_ERR_ARG, "workspace too small: need " + std::to_string(need));
+        pr.p.ws = static_cast<float *>(ws);
+    }
+    const hipStream_t hs = as_stream(stream);
+    hipError_t e = launch_gemm_both(res.tile, pr.fa, pr.fb, pr.p, hs);
+    if (e != hipSuccess) return hip_error(e, "both-sides 2:4 gemm launch");
+    if (pr.p.splits > 1) {
+        e = launch_splitk_reduce(pr.p, hs);
+        if (e != hipSuccess) return hip_error(e, "split-K reduce launch");
+    }
+    return FP8_OK;
 }
 
 fp8_status fp8_validate(const void *c, fp8_out c_type, int64_t ldc, const double *cref, const double *sabs, int64_t M,

@@ -349,7 +349,6 @@ template <int BM, int BN, int WM, int WN, bool ALONG_J, int LDS_BYTES>
 __device__ __forceinline__ void write_tile(const GemmParams &p, const v4f (&acc)[BM / WM / 16][BN / WN / 16], int m0,
                                            int n0, int wave, int lane, int split, uint8_t *smem)
 {
-    constexpr int NW = WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
     const int wm = wave / WN, wn = wave % WN;
@@ -652,7 +651,7 @@ __device__ __forceinline__ uint4 load_codes16(const uint8_t *row, int k, int len
     return load16_partial(row + k, max(0, min(16, len - k)), 0u);
 }
 
-template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP>
+template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool SPB = false>
 __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
 {
     constexpr int NT = WM * WN * 64;
@@ -661,7 +660,7 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
     using S = TileSmem<BM, BN, SP, kExactPF>;
     // work units per step: dense rows have 8 chunks of 16 codes, compressed
     // rows 4 chunks of 16 kept codes (32 dense positions each)
-    constexpr int A_U = SP ? BM * 4 : BM * 8, B_U = BN * 8;
+    constexpr int A_U = SP ? BM * 4 : BM * 8, B_U = SPB ? BN * 4 : BN * 8;
     constexpr int A_PER = (A_U + NT - 1) / NT, B_PER = (B_U + NT - 1) / NT;
     static_assert(TM >= 1 && TN >= 1, "wave tile");
 
@@ -676,7 +675,7 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
     const int Kv = p.K / 2, Km = p.K / 8;
 
     uint4 ra[A_PER], rb[B_PER];
-    uint32_t rm[SP ? A_PER : 1];
+    uint32_t rm[SP ? A_PER : 1], rmb[SPB ? B_PER : 1];
     auto gload = [&](int kt) {
         const int k0 = kbeg + kt * kBK;
 #pragma unroll
@@ -706,8 +705,23 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
         for (int u = 0; u < B_PER; ++u) {
             const int idx = tid + u * NT;
             if (B_U % NT != 0 && idx >= B_U) break;
-            const int r = idx >> 3, c = idx & 7, row = n0 + r;
-            rb[u] = row < p.N ? load_codes16(p.b + (int64_t)row * p.ldb, k0 + 16 * c, kend) : make_uint4(0, 0, 0, 0);
+            if constexpr (SPB) {
+                const int r = idx >> 2, c = idx & 3, row = n0 + r;
+                const int vk = k0 / 2 + 16 * c;
+                const int lim = min(Kv, kend / 2);
+                rb[u] = row < p.N ? load_codes16(p.b + (int64_t)row * p.ldb, vk, lim) : make_uint4(0, 0, 0, 0);
+                uint32_t m = 0;
+                if (row < p.N) {
+                    const uint8_t *mr = p.meta_b + (int64_t)row * p.ldmb + k0 / 8 + 4 * c;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (k0 / 8 + 4 * c + b < min(Km, kend / 8)) m |= (uint32_t)mr[b] << (8 * b);
+                }
+                rmb[u] = m;
+            } else {
+                const int r = idx >> 3, c = idx & 7, row = n0 + r;
+                rb[u] = row < p.N ? load_codes16(p.b + (int64_t)row * p.ldb, k0 + 16 * c, kend) : make_uint4(0, 0, 0, 0);
+            }
         }
     };
     // BF16 chunk x (8 codes) of row r sits at 16-byte slot x ^ (r & 15)
@@ -743,11 +757,23 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
         for (int u = 0; u < B_PER; ++u) {
             const int idx = tid + u * NT;
             if (B_U % NT != 0 && idx >= B_U) break;
-            const int r = idx >> 3, c = idx & 7;
-            uint4 lo, hi;
-            decode16<FB>(rb[u], lo, hi);
-            put(bb, r, 2 * c, lo);
-            put(bb, r, 2 * c + 1, hi);
+            if constexpr (SPB) {
+                const int r = idx >> 2, c = idx & 3;
+                uint4 d0, d1, b0, b1, b2, b3;
+                expand24(rb[u], rmb[u], d0, d1);
+                decode16<FB>(d0, b0, b1);
+                decode16<FB>(d1, b2, b3);
+                put(bb, r, 4 * c, b0);
+                put(bb, r, 4 * c + 1, b1);
+                put(bb, r, 4 * c + 2, b2);
+                put(bb, r, 4 * c + 3, b3);
+            } else {
+                const int r = idx >> 3, c = idx & 7;
+                uint4 lo, hi;
+                decode16<FB>(rb[u], lo, hi);
+                put(bb, r, 2 * c, lo);
+                put(bb, r, 2 * c + 1, hi);
+            }
         }
     };
 
@@ -807,14 +833,15 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
 // transposed output.  The 2:4 path never swaps (the compressed operand must
 // sit in the A slot).
 template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool KFAST = true, int PF = 2,
-          bool SWAP = !SP>
+          bool SWAP = !SP, bool SPB = false>
 __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
 {
     if constexpr (PF == kExactPF) {
-        gemm_tile_exact<BM, BN, WM, WN, FA, FB, SP>(p, tm, tn, split, smem);
+        gemm_tile_exact<BM, BN, WM, WN, FA, FB, SP, SPB>(p, tm, tn, split, smem);
         return;
     } else if constexpr (PF >= 6) {
         static_assert(KFAST, "the DMA pipeline needs whole 16-byte chunks");
+        static_assert(!SPB, "a compressed j operand takes the register pipeline");
         if constexpr (SP && BM % 64 != 0) {
             // the metadata of fewer than 64 rows does not fill a 1 KiB DMA
             // block: such 2:4 tiles (BM <= 32) take the register pipeline
@@ -831,7 +858,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
     using S = TileSmem<BM, BN, SP, PF>;
     constexpr int A_CH = SP ? BM * 4 : BM * 8;     // 16-byte chunks per stage
     constexpr int M_CH = SP ? BM : 0;
-    constexpr int B_CH = BN * 8;
+    // a compressed j operand (SPB) loads 16-byte chunks of kept codes (32
+    // dense positions each) plus their 4 metadata bytes and is expanded to
+    // dense rows on its way into LDS
+    constexpr int B_CH = SPB ? BN * 4 : BN * 8;
     constexpr int A_PER = (A_CH + NT - 1) / NT, B_PER = (B_CH + NT - 1) / NT;
     constexpr int M_PER = (M_CH + NT - 1) / NT;
     static_assert(PF >= 6 || ((A_CH % NT == 0 || A_CH < NT) && (B_CH % NT == 0 || B_CH < NT)),
@@ -849,6 +879,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
     const int Kv = p.K / 2, Km = p.K / 8;   // compressed row lengths
 
     uint4 ra[PF][A_PER], rb[PF][B_PER], rm[PF][M_PER > 0 ? M_PER : 1];
+    uint32_t rmb[PF][SPB ? B_PER : 1];
 
     // Chunks past the end of K are zeroed (metadata: given a valid filler)
     // when the registers are written to LDS, after the MFMAs of the step, so
@@ -867,13 +898,17 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
     const __amdgpu_buffer_rsrc_t rs_m = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(SP ? p.meta + (int64_t)m0 * p.ldm : p.a), (short)0, SP ? rows_a * (int)p.ldm : 0, kBufferFlags);
     const int voff_a = SP ? (tid >> 2) * (int)p.lda + (tid & 3) * 16 : (tid >> 3) * (int)p.lda + (tid & 7) * 16;
-    const int voff_b = (tid >> 3) * (int)p.ldb + (tid & 7) * 16;
+    const int voff_b = SPB ? (tid >> 2) * (int)p.ldb + (tid & 3) * 16 : (tid >> 3) * (int)p.ldb + (tid & 7) * 16;
+    const __amdgpu_buffer_rsrc_t rs_mb = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(SPB ? p.meta_b + (int64_t)n0 * p.ldmb : p.b), (short)0, SPB ? rows_b * (int)p.ldmb : 0,
+        kBufferFlags);
+    const int voff_mb = SPB ? (tid >> 2) * (int)p.ldmb + (tid & 3) * 4 : 0;
     const int voff_m = tid * (int)p.ldm;
     auto bload = [](const __amdgpu_buffer_rsrc_t &r, int voff, int soff) {
         const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
         return make_uint4(v[0], v[1], v[2], v[3]);
     };
-    auto gload = [&](int kt, uint4 *ra, uint4 *rb, uint4 *rm) {
+    auto gload = [&](int kt, uint4 *ra, uint4 *rb, uint4 *rm, uint32_t *rmb) {
         const int k0 = kbeg + kt * kBK;
         if constexpr (kfast) {
 #pragma unroll
@@ -890,7 +925,13 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
 #pragma unroll
             for (int u = 0; u < B_PER; ++u) {
                 if (B_CH < NT && tid + u * NT >= B_CH) break;
-                rb[u] = bload(rs_b, voff_b, u * (NT / 8) * (int)p.ldb + k0);
+                if constexpr (SPB) {
+                    rb[u] = bload(rs_b, voff_b, u * (NT / 4) * (int)p.ldb + k0 / 2);
+                    rmb[u] = __builtin_amdgcn_raw_buffer_load_b32(rs_mb, voff_mb, u * (NT / 4) * (int)p.ldmb + k0 / 8,
+                                                                  0);
+                } else {
+                    rb[u] = bload(rs_b, voff_b, u * (NT / 8) * (int)p.ldb + k0);
+                }
             }
             return;
         }
@@ -928,11 +969,24 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
         for (int u = 0; u < B_PER; ++u) {
             const int idx = tid + u * NT;
             if (B_CH < NT && idx >= B_CH) break;
-            const int r = idx >> 3, c = idx & 7;
-            const int row = n0 + r;
-            const int kk = k0 + c * 16;
-            const uint8_t *src = p.b + (int64_t)(row < p.N ? row : 0) * p.ldb;
-            rb[u] = load16_partial(src + kk, row < p.N ? min(16, max(0, kend - kk)) : 0, 0u);
+            if constexpr (SPB) {
+                const int r = idx >> 2, c = idx & 3;
+                const int row = n0 + r;
+                const int vk = k0 / 2 + c * 16, mk = k0 / 8 + c * 4;
+                const int64_t off = (int64_t)(row < p.N ? row : 0);
+                rb[u] = load16_partial(p.b + off * p.ldb + vk, row < p.N ? min(16, max(0, Kv - vk)) : 0, 0u);
+                uint32_t m = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (row < p.N && mk + t < Km) m |= (uint32_t)p.meta_b[off * p.ldmb + mk + t] << (8 * t);
+                rmb[u] = m;
+            } else {
+                const int r = idx >> 3, c = idx & 7;
+                const int row = n0 + r;
+                const int kk = k0 + c * 16;
+                const uint8_t *src = p.b + (int64_t)(row < p.N ? row : 0) * p.ldb;
+                rb[u] = load16_partial(src + kk, row < p.N ? min(16, max(0, kend - kk)) : 0, 0u);
+            }
         }
     };
 
@@ -940,7 +994,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
         return ok ? v : make_uint4(fill, fill, fill, fill);
     };
 
-    auto sstore = [&](int buf, const uint4 *ra, const uint4 *rb, const uint4 *rm, int kt) {
+    auto sstore = [&](int buf, const uint4 *ra, const uint4 *rb, const uint4 *rm, const uint32_t *rmb, int kt) {
         const int k0 = kbeg + kt * kBK;
         uint8_t *base = smem + buf * S::STAGE;
 #pragma unroll
@@ -969,8 +1023,17 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
         for (int u = 0; u < B_PER; ++u) {
             const int idx = tid + u * NT;
             if (B_CH < NT && idx >= B_CH) break;
-            const int r = idx >> 3, c = idx & 7;
-            *reinterpret_cast<uint4 *>(bb + swz(r, c)) = kfast ? sel(rb[u], k0 + c * 16 < kend, 0u) : rb[u];
+            if constexpr (SPB) {
+                // kept codes past the end of K (zeros) expand to zeros
+                const int r = idx >> 2, c = idx & 3;
+                uint4 d0, d1;
+                expand24(kfast ? sel(rb[u], k0 / 2 + c * 16 < Kv, 0u) : rb[u], rmb[u], d0, d1);
+                *reinterpret_cast<uint4 *>(bb + swz(r, 2 * c)) = d0;
+                *reinterpret_cast<uint4 *>(bb + swz(r, 2 * c + 1)) = d1;
+            } else {
+                const int r = idx >> 3, c = idx & 7;
+                *reinterpret_cast<uint4 *>(bb + swz(r, c)) = kfast ? sel(rb[u], k0 + c * 16 < kend, 0u) : rb[u];
+            }
         }
     };
 
@@ -1081,10 +1144,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
         AFrag a0, a1;
         int s0 = 0, s1 = 1, s2 = 2;   // stages of steps k, k+1, k+2
         if (nk > 0) {
-            gload(0, ra[0], rb[0], rm[0]);
-            sstore(0, ra[0], rb[0], rm[0], 0);
-            gload(1, ra[0], rb[0], rm[0]);
-            sstore(1, ra[0], rb[0], rm[0], 1);
+            gload(0, ra[0], rb[0], rm[0], rmb[0]);
+            sstore(0, ra[0], rb[0], rm[0], rmb[0], 0);
+            gload(1, ra[0], rb[0], rm[0], rmb[0]);
+            sstore(1, ra[0], rb[0], rm[0], rmb[0], 1);
             __syncthreads();
             read_b(0, gb0);
             a0 = read_a(0, 0);
@@ -1096,29 +1159,29 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
             s2 = t;
         };
         for (int kt = 0; kt < nk; kt += 2) {
-            gload(kt + 2, ra[0], rb[0], rm[0]);
+            gload(kt + 2, ra[0], rb[0], rm[0], rmb[0]);
             step(s0, gb0, a0, s1, gb1, a1);
-            sstore(s2, ra[0], rb[0], rm[0], kt + 2);
+            sstore(s2, ra[0], rb[0], rm[0], rmb[0], kt + 2);
             __syncthreads();
             rot();
             if (kt + 1 >= nk) break;
-            gload(kt + 3, ra[0], rb[0], rm[0]);
+            gload(kt + 3, ra[0], rb[0], rm[0], rmb[0]);
             step(s0, gb1, a1, s1, gb0, a0);
-            sstore(s2, ra[0], rb[0], rm[0], kt + 3);
+            sstore(s2, ra[0], rb[0], rm[0], rmb[0], kt + 3);
             __syncthreads();
             rot();
         }
     } else if constexpr (PF == 1) {
         // Loads of step k+1 go to the single register set during step k.
         if (nk > 0) {
-            gload(0, ra[0], rb[0], rm[0]);
-            sstore(0, ra[0], rb[0], rm[0], 0);
+            gload(0, ra[0], rb[0], rm[0], rmb[0]);
+            sstore(0, ra[0], rb[0], rm[0], rmb[0], 0);
             __syncthreads();
         }
         for (int kt = 0; kt < nk; ++kt) {
-            if (kt + 1 < nk) gload(kt + 1, ra[0], rb[0], rm[0]);
+            if (kt + 1 < nk) gload(kt + 1, ra[0], rb[0], rm[0], rmb[0]);
             compute(kt & 1);
-            if (kt + 1 < nk) sstore((kt + 1) & 1, ra[0], rb[0], rm[0], kt + 1);
+            if (kt + 1 < nk) sstore((kt + 1) & 1, ra[0], rb[0], rm[0], rmb[0], kt + 1);
             __syncthreads();
         }
     } else {
@@ -1129,20 +1192,20 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
         // nobody reads), which keeps the wait counts exact: the stores of a
         // step wait only for the loads issued a step earlier.
         if (nk > 0) {
-            gload(0, ra[0], rb[0], rm[0]);
-            gload(1, ra[PF - 1], rb[PF - 1], rm[PF - 1]);
-            sstore(0, ra[0], rb[0], rm[0], 0);
+            gload(0, ra[0], rb[0], rm[0], rmb[0]);
+            gload(1, ra[PF - 1], rb[PF - 1], rm[PF - 1], rmb[PF - 1]);
+            sstore(0, ra[0], rb[0], rm[0], rmb[0], 0);
             __syncthreads();
         }
         for (int kt = 0; kt < nk; kt += 2) {
-            gload(kt + 2, ra[0], rb[0], rm[0]);
+            gload(kt + 2, ra[0], rb[0], rm[0], rmb[0]);
             compute(0);
-            sstore(1, ra[PF - 1], rb[PF - 1], rm[PF - 1], kt + 1);
+            sstore(1, ra[PF - 1], rb[PF - 1], rm[PF - 1], rmb[PF - 1], kt + 1);
             __syncthreads();
             if (kt + 1 >= nk) break;
-            gload(kt + 3, ra[PF - 1], rb[PF - 1], rm[PF - 1]);
+            gload(kt + 3, ra[PF - 1], rb[PF - 1], rm[PF - 1], rmb[PF - 1]);
             compute(1);
-            sstore(0, ra[0], rb[0], rm[0], kt + 2);
+            sstore(0, ra[0], rb[0], rm[0], rmb[0], kt + 2);
             __syncthreads();
         }
     }

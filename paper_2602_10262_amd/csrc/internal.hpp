@@ -9,18 +9,20 @@ constexpr int kBKHost = 128;   // K step of every GEMM kernel (codes)
 
 // One GEMM as the kernels see it.  The "i" operand sits in the MFMA A slot
 // (dense rows, or 2:4-compressed values + metadata when sparse), the "j"
-// operand in the MFMA B slot (always dense rows of K codes).  The result
+// operand in the MFMA B slot (dense rows of K codes, or 2:4-compressed rows
+// that the kernel expands to dense ones on their way into LDS).  The result
 // element (i, j) is stored at c[i*ldc + j], or at c[j*ldc + i] when
 // trans_out is set (used when the compressed operand is the weight).
 struct GemmParams {
     const uint8_t *a;      // i operand: dense M x K (lda) or compressed values M x K/2 (lda)
     const uint8_t *meta;   // i operand metadata M x K/8 (ldm) when sparse
-    const uint8_t *b;      // j operand: N x K (ldb)
+    const uint8_t *b;      // j operand: N x K (ldb), or compressed values N x K/2 when meta_b is set
+    const uint8_t *meta_b; // j operand metadata N x K/8 (ldmb) when both operands are 2:4-compressed
     const float *si;       // descale of row i (or one for all rows)
     const float *sj;       // descale of column j (or one)
     void *c;
     float *ws;             // split-K partial sums [splits][M][N] when splits > 1
-    int64_t lda, ldm, ldb, ldc;
+    int64_t lda, ldm, ldb, ldc, ldmb;
     int M, N, K;
     int si_per, sj_per;    // 1: one descale per row / column
     int out_bf16;
@@ -49,9 +51,21 @@ const TileDesc &tile_desc(int t);
 bool k_is_fast(bool sparse, int K);
 hipError_t launch_gemm(int tile, int fa, int fb, bool sparse, const GemmParams &p, hipStream_t st);
 hipError_t launch_splitk_reduce(const GemmParams &p, hipStream_t st);
+// Both operands compressed (p.meta and p.meta_b set): tiles that have such a
+// kernel, and its launch.
+bool both_tile_supported(int tile);
+hipError_t launch_gemm_both(int tile, int fa, int fb, const GemmParams &p, hipStream_t st);
 
 hipError_t launch_quantize(const float *x, int64_t rows, int64_t cols, int64_t ldx, int fmt, int per_row,
                            uint8_t *q, int64_t ldq, float *s, float *d, void *ws, hipStream_t st);
+// Clears *amax_bits and reduces max |x| (FP32 bit pattern) into it.
+hipError_t launch_amax_tensor(const float *x, int64_t rows, int64_t cols, int64_t ldx, uint32_t *amax_bits,
+                              hipStream_t st);
+// Quantize (per tensor or per row) and 2:4 prune/compress in one pass; ws
+// holds the amax word of the per-tensor form.
+hipError_t launch_quantize_prune24(const float *x, int64_t rows, int64_t K, int64_t ldx, int fmt, int per_row,
+                                   uint8_t *values, uint8_t *meta, uint8_t *mask, float *s, float *d, void *ws,
+                                   hipStream_t st);
 hipError_t launch_encode_bits(int fmt, uint32_t lo, int64_t n, uint8_t *out, hipStream_t st);
 
 hipError_t launch_prune24(const uint8_t *x, int64_t rows, int64_t K, int64_t ldx, uint8_t *values,

@@ -243,6 +243,14 @@ hipError_t launch_quantize(const float *x, int64_t rows, int64_t cols, int64_t l
     return hipGetLastError();
 }
 
+hipError_t launch_amax_tensor(const float *x, int64_t rows, int64_t cols, int64_t ldx, uint32_t *amax_bits,
+                              hipStream_t st)
+{
+    amax_clear<<<1, 1, 0, st>>>(amax_bits);
+    amax_tensor<<<grid_for(rows * ((cols + 15) / 16)), kQThreads, 0, st>>>(x, rows, cols, ldx, amax_bits);
+    return hipGetLastError();
+}
+
 hipError_t launch_encode_bits(int fmt, uint32_t lo, int64_t n, uint8_t *out, hipStream_t st)
 {
     if (fmt == kE4M3)

@@ -14,32 +14,6 @@ namespace fp8k {
 
 constexpr int kPThreads = 256;
 
-// Survivors of one group of four codes packed in w (byte t = position t).
-// Returns nibble i0 | i1 << 2 and the two survivor codes (v0 at i0, v1 at i1).
-__device__ __forceinline__ uint32_t prune_group(uint32_t w, uint32_t &vals, uint32_t &keep4)
-{
-    uint32_t k[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) k[t] = (w >> (8 * t)) & 0x7Fu;
-    uint32_t keep = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int beaten = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (j == i) continue;
-            beaten += (k[j] > k[i]) || (k[j] == k[i] && j < i);
-        }
-        keep |= (beaten < 2 ? 1u : 0u) << i;
-    }
-    // keep has exactly two bits set: lowest is i0, highest is i1
-    const uint32_t i0 = (uint32_t)__builtin_ctz(keep);
-    const uint32_t i1 = 31u - (uint32_t)__builtin_clz(keep);
-    vals = ((w >> (8 * i0)) & 0xFFu) | (((w >> (8 * i1)) & 0xFFu) << 8);
-    keep4 = keep;
-    return i0 | (i1 << 2);
-}
-
 __global__ void __launch_bounds__(kPThreads) prune24_kernel(const uint8_t *x, int64_t rows, int64_t K,
                                                             int64_t ldx, uint8_t *values, uint8_t *meta,
                                                             uint8_t *mask)

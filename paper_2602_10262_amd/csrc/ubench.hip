@@ -7,14 +7,18 @@
 // independent accumulator chains of one instruction for `iters` rounds.  With
 // chains = 1 every instruction waits for the previous one: the dependent
 // issue latency.  Operands are fixed register values (throughput does not
-// depend on them).  LDS kernel: every wave reads 16 bytes per lane with
-// ds_read_b128 from a conflict-free pattern, `iters` times.
+// depend on them).  LDS kernels: every wave reads 16 bytes per lane with
+// ds_read_b128 (4 with ds_read_b32 for the metadata pattern) `iters` times,
+// either from a linear pattern or from the address patterns of the GEMM
+// fragment reads, so bank conflicts of those patterns show up in time and in
+// the LDS conflict counters.
 #include <hip/hip_runtime.h>
 
 #include <string>
 
 #include "api_util.hpp"
 #include "common.hpp"
+#include "gemm_tile.hpp"
 
 namespace fp8k {
 
@@ -62,18 +66,40 @@ __global__ void __launch_bounds__(1024) mfma_rate(float *sink, int iters, int se
     if (s == 1234.5f) sink[threadIdx.x] = s;   // keeps the chains alive; never true for these operands
 }
 
+// LDS read patterns: 0 linear 16-byte slots; the GEMM fragment reads of one
+// 16 x 128 K step, each lane l reading row (l % 16) of a 16-row block at
+// chunk positions g = l / 16: 1 dense operand (128-byte rows, chunk 2g, the
+// swizzle of the dense tiles), 2 compressed operand (64-byte rows, chunk g,
+// its swizzle), 3 dense operand read as the 2:4 B operand (chunk g + 4), 4
+// metadata (16-byte rows, a 4-byte word g: ds_read_b32), 5 compressed
+// operand without swizzle (row r at r * 64).  Successive iterations move to
+// the next 16-row block (mod 256 rows).
+template <int P>
 __global__ void __launch_bounds__(1024) lds_rate(float *sink, int iters)
 {
     extern __shared__ uint4 lds_buf[];
-    // 64 KiB of LDS: lane l of wave w reads 16-byte slot (w * 64 + l + it) % 4096
-    const int slots = 4096;
+    const int slots = 4096;   // 64 KiB
     for (int i = threadIdx.x; i < slots; i += blockDim.x) lds_buf[i] = make_uint4(i, i + 1, i + 2, i + 3);
     __syncthreads();
+    const uint8_t *bytes = reinterpret_cast<const uint8_t *>(lds_buf);
     uint4 acc = make_uint4(0, 0, 0, 0);
-    const int base = threadIdx.x;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l & 15, lg = l >> 4;
     for (int it = 0; it < iters; ++it) {
-        const uint4 v = lds_buf[(base + it * 64) & (slots - 1)];
-        acc.x ^= v.x; acc.y += v.y; acc.z ^= v.z; acc.w += v.w;
+        const int r = ((it + w) * 16 + lr) & 255;
+        if constexpr (P == 4) {
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(bytes + r * 16 + lg * 4);
+            acc.x ^= v;
+            acc.y += v;
+        } else {
+            int off;
+            if constexpr (P == 0) off = ((threadIdx.x + it * 64) & (slots - 1)) * 16;
+            else if constexpr (P == 1) off = swz(r, 2 * lg);
+            else if constexpr (P == 2) off = swz_sp(r, lg);
+            else if constexpr (P == 3) off = swz(r, lg + 4);
+            else off = r * 64 + lg * 16;
+            const uint4 v = *reinterpret_cast<const uint4 *>(bytes + off);
+            acc.x ^= v.x; acc.y += v.y; acc.z ^= v.z; acc.w += v.w;
+        }
     }
     if (acc.x == 0x12345678u && acc.y == 7u) sink[threadIdx.x] = 1.f;
 }
@@ -146,8 +172,9 @@ fp8_status fp8_ubench_mfma(int kind, int waves_per_cu, int chains, int iters, vo
     return FP8_OK;
 }
 
-fp8_status fp8_ubench_lds(int waves_per_cu, int iters, void *stream, double *ms)
+fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void *stream, double *ms)
 {
+    if (pattern < 0 || pattern > 5) return set_error(FP8_ERR_ARG, "pattern must be 0..5");
     if (waves_per_cu < 1 || waves_per_cu > 16 || iters < 1 || !ms) return set_error(FP8_ERR_ARG, "bad arguments");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     float *sink = nullptr;
@@ -157,14 +184,33 @@ fp8_status fp8_ubench_lds(int waves_per_cu, int iters, void *stream, double *ms)
     int cus = 256, dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    e = hipFuncSetAttribute((const void *)lds_rate, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *fn = nullptr;
+    switch (pattern) {
+    case 0: fn = (const void *)lds_rate<0>; break;
+    case 1: fn = (const void *)lds_rate<1>; break;
+    case 2: fn = (const void *)lds_rate<2>; break;
+    case 3: fn = (const void *)lds_rate<3>; break;
+    case 4: fn = (const void *)lds_rate<4>; break;
+    default: fn = (const void *)lds_rate<5>; break;
+    }
+    auto go = [&](int it) {
+        switch (pattern) {
+        case 0: lds_rate<0><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
+        case 1: lds_rate<1><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
+        case 2: lds_rate<2><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
+        case 3: lds_rate<3><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
+        case 4: lds_rate<4><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
+        default: lds_rate<5><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
+        }
+    };
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     if (e == hipSuccess) {
-        lds_rate<<<cus, waves_per_cu * 64, lds, st>>>(sink, 16);
+        go(16);
         (void)hipEventRecord(e0, st);
-        lds_rate<<<cus, waves_per_cu * 64, lds, st>>>(sink, iters);
+        go(iters);
         (void)hipEventRecord(e1, st);
         e = hipGetLastError();
     }
@@ -177,6 +223,11 @@ fp8_status fp8_ubench_lds(int waves_per_cu, int iters, void *stream, double *ms)
     if (e != hipSuccess) return hip_error(e, "LDS microbenchmark launch");
     *ms = t;
     return FP8_OK;
+}
+
+fp8_status fp8_ubench_lds(int waves_per_cu, int iters, void *stream, double *ms)
+{
+    return fp8_ubench_lds_pattern(0, waves_per_cu, iters, stream, ms);
 }
 
 }  // extern "C"

@@ -119,3 +119,61 @@ def test_prune_full_size_bit_exact(gpu):
     assert np.array_equal(values[sel].cpu().numpy(), v)
     assert np.array_equal(meta[sel].cpu().numpy(), m)
     assert np.array_equal(mask[sel].cpu().numpy(), k)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("per_row", [False, True])
+@pytest.mark.parametrize("shape,dist", [((256, 256), "uniform"), ((37, 56), "normal"), ((1, 8), "normal"),
+                                        ((300, 1000), "normal"), ((5, 4096), "uniform"), ((3, 8200), "normal"),
+                                        ((2, 12288), "normal"), ((2, 16384), "uniform"), ((2, 16392), "normal")])
+def test_quantize_prune_fused_bit_exact(gpu, fmt, per_row, shape, dist):
+    """The one-pass encode equals the oracle's quantize followed by its 2:4
+    prune: codes of the survivors, metadata, mask and scales bit for bit
+    (K % 16 == 8 rows end in a half unit; K > 16384 takes the two-read form)."""
+    import torch
+    rows, K = shape
+    x = synth.uniform(5, 9, shape) if dist == "uniform" else synth.normal_outliers(6, shape)
+    ld = (K + 3) // 4 * 4
+    xd = torch.zeros((rows, ld), dtype=torch.float32, device="cuda")
+    xd[:, :K] = dev(x)
+    kind = gpu.FP8_SCALE_ROW if per_row else gpu.FP8_SCALE_TENSOR
+    values, meta, mask, s, d = gpu.fp8_quantize_prune24(xd[:, :K], fmt, kind)
+    torch.cuda.synchronize()
+    qo, so, do = orc.quantize(x, fmt, per_row)
+    v, m, k, _ = orc.prune24(qo, fmt)
+    log(f"quantize+prune fmt={fmt} per_row={per_row} shape={shape}")
+    assert np.array_equal(values.cpu().numpy(), v)
+    assert np.array_equal(meta.cpu().numpy(), m)
+    assert np.array_equal(mask.cpu().numpy(), k)
+    assert np.array_equal(s.cpu().numpy().view(np.uint32), so.view(np.uint32))
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), do.view(np.uint32))
+
+
+@pytest.mark.parametrize("per_row", [False, True])
+def test_quantize_prune_fused_full_size(gpu, per_row):
+    """8192 x 8192 (the headline operand): the fused pass equals quantize then
+    prune on the GPU bit for bit, and sampled rows equal the oracle's."""
+    import torch
+    rows = K = 8192
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.randn((rows, K), dtype=torch.float32, device="cuda", generator=g)
+    kind = gpu.FP8_SCALE_ROW if per_row else gpu.FP8_SCALE_TENSOR
+    values, meta, mask, s, d = gpu.fp8_quantize_prune24(x, 0, kind)
+    q, s2, d2 = gpu.fp8_quantize(x, 0, kind)
+    v2, m2, k2 = gpu.fp8_sparse24_prune_compress(q, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(values, v2) and torch.equal(meta, m2) and torch.equal(mask, k2)
+    assert torch.equal(s.view(torch.int32), s2.view(torch.int32))
+    assert torch.equal(d.view(torch.int32), d2.view(torch.int32))
+    sel = [0, 1, 4095, rows - 1]
+    xh = x[sel].cpu().numpy()
+    if per_row:
+        qo, so, _ = orc.quantize(xh, 0, True)
+        assert np.array_equal(s[sel].cpu().numpy().view(np.uint32), so.view(np.uint32))
+    else:
+        # the per-tensor scale of the whole matrix applied to the sampled rows
+        qo = orc.encode(0, (xh * s.cpu().numpy()[0]).astype(np.float32).ravel()).reshape(xh.shape)
+    vo, mo, ko, _ = orc.prune24(qo, 0)
+    assert np.array_equal(values[sel].cpu().numpy(), vo)
+    assert np.array_equal(meta[sel].cpu().numpy(), mo)
+    assert np.array_equal(mask[sel].cpu().numpy(), ko)
