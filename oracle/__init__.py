@@ -19,7 +19,7 @@ import numpy as np
 
 E4M3, E5M2 = 0, 1
 FMAX = {E4M3: 448.0, E5M2: 57344.0}
-OUT_F32, OUT_BF16 = 0, 1
+OUT_F32, OUT_BF16, OUT_F16 = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -61,6 +61,7 @@ def _load():
     lib.orc_decompress24.argtypes = [P, P, I64, I64, P]
     lib.orc_gemm.argtypes = [P, I, I64, P, I, I64, P, I, P, I, I64, I64, I64, I64, I64, P, P, I]
     lib.orc_gemm_at.argtypes = [P, I, I64, P, I, I64, P, I, P, I, I64, P, P, I64, P, P]
+    lib.orc_gemm_real.argtypes = [P, I64, P, I64, P, I, P, I, I64, I64, I64, P, P, I]
     _lib = lib
     return lib
 
@@ -211,21 +212,50 @@ def gemm_at(a: np.ndarray, a_fmt: int, b_nk: np.ndarray, b_fmt: int, da, db, ii,
     return cref, sabs
 
 
+def gemm_real(a: np.ndarray, b_nk: np.ndarray, sa=1.0, sb=1.0, nthreads: int | None = None):
+    """FP64 (C_ref, S_abs) for C = diag(s_a) A B diag(s_b) with real-valued
+    operands (FP32, FP16 or BF16 arrays, or FP64 holding such values).
+
+    a: M x K (row-major); b_nk: N x K (B column-major); sa: 1 or M floats;
+    sb: 1 or N floats."""
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b_nk = np.ascontiguousarray(b_nk, dtype=np.float64)
+    M, K = a.shape
+    N, K2 = b_nk.shape
+    assert K == K2
+    sa = np.ascontiguousarray(np.atleast_1d(np.asarray(sa, dtype=np.float32)))
+    sb = np.ascontiguousarray(np.atleast_1d(np.asarray(sb, dtype=np.float32)))
+    assert sa.size in (1, M) and sb.size in (1, N)
+    cref = np.zeros((M, N), np.float64)
+    sabs = np.zeros((M, N), np.float64)
+    nt = nthreads or os.cpu_count() or 1
+    lib.orc_gemm_real(_ptr(a), K, _ptr(b_nk), K, _ptr(sa), int(sa.size > 1), _ptr(sb), int(sb.size > 1),
+                      M, N, K, _ptr(cref), _ptr(sabs), nt)
+    return cref, sabs
+
+
 # --------------------------------------------------------------------------
 # Acceptance bound
 # --------------------------------------------------------------------------
 
 U32 = 2.0 ** -24     # unit roundoff of FP32
 UBF16 = 2.0 ** -8    # unit roundoff of BF16 (8 significant bits)
+UF16 = 2.0 ** -11    # unit roundoff of FP16 (11 significant bits)
+F16_SUB_HALF = 2.0 ** -25   # half the spacing of FP16 subnormals
 
 
 def bound(sabs: np.ndarray, cref: np.ndarray, K: int, out_type: int) -> np.ndarray:
     """Elementwise tolerance: 4 K u S_abs for FP32 output; for BF16 output the
     FP32 bound grown by one BF16 round-to-nearest step:
-    (1 + 2^-8) 4 K u S_abs + 2^-8 |C_ref|."""
+    (1 + 2^-8) 4 K u S_abs + 2^-8 |C_ref|; for FP16 output likewise with
+    2^-11, plus 2^-25 for results in the FP16 subnormal range (in range: no
+    result may exceed the FP16 maximum)."""
     base = 4.0 * K * U32 * sabs
     if out_type == OUT_F32:
         return base
+    if out_type == OUT_F16:
+        return (1.0 + UF16) * base + UF16 * np.abs(cref) + F16_SUB_HALF
     return (1.0 + UBF16) * base + UBF16 * np.abs(cref)
 
 

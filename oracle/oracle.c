@@ -437,6 +437,70 @@ void orc_gemm_at(const uint8_t *a, int a_fmt, int64_t lda, const uint8_t *b, int
 }
 
 /* ------------------------------------------------------------------------- */
+/* GEMM of real-valued operands in FP64 (the FP32 / FP16 / BF16 stages).       */
+/* ------------------------------------------------------------------------- */
+
+/* The mixed-precision sequence of Sec. 8.3 runs FP32 and 16-bit GEMM stages
+ * beside the FP8 one.  Their definition, with a and b the exact FP64 values
+ * of the stage's FP32, FP16 or BF16 inputs:
+ *   C_ref[i,j] = s_a[i] * s_b[j] * sum_k a[i,k] * b[j,k]
+ *   S_abs[i,j] = |s_a[i] * s_b[j]| * sum_k |a[i,k] * b[j,k]|
+ * a: row-major M x K (lda); b: N rows of K (ldb), i.e. B column-major; s_a
+ * has M entries if a_per_row else 1, s_b N entries if b_per_col else 1.  A
+ * product of two such values has at most 48 significant bits and is exact
+ * in FP64; the FP64 sum (k ascending) errs by at most K 2^-53 S_abs, a
+ * 2^-29 fraction of the acceptance bound 4 K 2^-24 S_abs. */
+typedef struct {
+    const double *a; int64_t lda;
+    const double *b; int64_t ldb;
+    const float *sa; int a_per_row;
+    const float *sb; int b_per_col;
+    int64_t N, K;
+    double *cref, *sabs;
+    int64_t row_lo, row_hi;
+} real_job;
+
+static void *real_worker(void *p)
+{
+    real_job *j = (real_job *)p;
+    for (int64_t i = j->row_lo; i < j->row_hi; ++i) {
+        for (int64_t jj = 0; jj < j->N; ++jj) {
+            double sum = 0.0, asum = 0.0;
+            for (int64_t k = 0; k < j->K; ++k) {
+                double prod = j->a[i * j->lda + k] * j->b[jj * j->ldb + k];
+                sum += prod;
+                asum += fabs(prod);
+            }
+            double sa = j->sa[j->a_per_row ? i : 0], sb = j->sb[j->b_per_col ? jj : 0];
+            j->cref[i * j->N + jj] = (sum * sa) * sb;
+            j->sabs[i * j->N + jj] = fabs(sa * sb) * asum;
+        }
+    }
+    return NULL;
+}
+
+void orc_gemm_real(const double *a, int64_t lda, const double *b, int64_t ldb, const float *sa, int a_per_row,
+                   const float *sb, int b_per_col, int64_t M, int64_t N, int64_t K, double *cref, double *sabs,
+                   int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    real_job jobs[256];
+    pthread_t th[256];
+    int64_t step = (M + nthreads - 1) / nthreads;
+    for (int t = 0; t < nthreads; ++t) {
+        real_job *j = &jobs[t];
+        j->a = a; j->lda = lda; j->b = b; j->ldb = ldb;
+        j->sa = sa; j->a_per_row = a_per_row; j->sb = sb; j->b_per_col = b_per_col;
+        j->N = N; j->K = K; j->cref = cref; j->sabs = sabs;
+        j->row_lo = step * t < M ? step * t : M;
+        j->row_hi = step * (t + 1) < M ? step * (t + 1) : M;
+        pthread_create(&th[t], NULL, real_worker, j);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Batch encode of consecutive FP32 bit patterns (for exhaustive checks).      */
 /* ------------------------------------------------------------------------- */
 
