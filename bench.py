@@ -341,6 +341,49 @@ def bench_sparse(lib, qa, da, qb, db, iters, warmup, stream):
     }
 
 
+def bench_mixed(lib, stream, M=4096, H=2048, n_chains=8, streams=4):
+    """Mixed-precision sequence: the FP32 / FP16 / BF16 GEMMs alone at H^3,
+    then n_chains chains of FP32 -> FP16 -> FP8 stages (M x H each) under the
+    three schedules of the chain executor."""
+    import torch
+    res = {"gemm": [], "chains": {}}
+    g = torch.Generator(device="cuda").manual_seed(3)
+    for name, dt in (("f32", torch.float32), ("f16", torch.float16), ("bf16", torch.bfloat16)):
+        a = torch.randn((4096, 4096), generator=g, device="cuda").to(dt)
+        b = torch.randn((4096, 4096), generator=g, device="cuda").to(dt)
+        c = torch.empty((4096, 4096), dtype=torch.float32, device="cuda")
+        lib.fp8_hp_gemm(a, b, c=c, stream=stream)
+        ms = time_events(lambda: lib.fp8_hp_gemm(a, b, c=c, stream=stream), 10, stream)
+        peak = 157.3 if name == "f32" else 2500.0
+        tf = 2.0 * 4096 ** 3 / (ms * 1e-3) / 1e12
+        res["gemm"].append({"type": name, "shape": [4096, 4096, 4096], "ms": ms, "tflops": tf,
+                            "frac_of_peak": tf / peak})
+        del a, b, c
+    stages, keep = [], []
+    for p, dt in ((lib.FP8_STAGE_F32, torch.float32), (lib.FP8_STAGE_F16, torch.float16), (lib.FP8_STAGE_FP8, None)):
+        w = torch.randn((H, H), generator=g, device="cuda") / H ** 0.5
+        if p == lib.FP8_STAGE_FP8:
+            q, _, d = lib.fp8_quantize(w, 0, lib.FP8_SCALE_ROW, stream=stream)
+            stages.append((p, q, d))
+        else:
+            stages.append((p, w.to(dt), None))
+    torch.cuda.synchronize()
+    ch = lib.Chain(stages, M, H, n_chains, max_streams=streams)
+    for c in range(n_chains):
+        ch.tensor(c, 0).copy_(torch.randn((M, H), generator=g, device="cuda"))
+    torch.cuda.synchronize()
+    res["chains"]["config"] = {"M": M, "H": H, "n_chains": n_chains, "streams": streams,
+                               "stages": ["f32", "f16", "fp8"]}
+    for name, sched, ns in (("serial", lib.FP8_CHAIN_SERIAL, 1), ("in_phase", lib.FP8_CHAIN_IN_PHASE, streams),
+                            ("staggered", lib.FP8_CHAIN_STAGGERED, streams)):
+        ch.run(sched, ns)   # warm-up
+        runs = [ch.run(sched, ns) for _ in range(3)]
+        best = min(runs, key=lambda r: r["makespan_ms"])
+        res["chains"][name] = best
+    ch.close()
+    return res
+
+
 def bench_encode(lib, stream, sizes=(256, 512, 2048, 8192)):
     """The 2:4 encode step (the overhead the paper measures apart from the
     GEMM): FP32 -> codes -> pruned and compressed, per-row scales, as two
@@ -645,6 +688,7 @@ def main():
                     help="served stream at 0.25..2.0 x serial capacity and 1, 2, 8 GiB budgets")
     ap.add_argument("--ace-only", action="store_true", help="only the concurrent-stream study (for counter runs)")
     ap.add_argument("--ubench-only", action="store_true", help="only the matrix-core and LDS microbenchmarks")
+    ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision GEMMs and chains")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the headline GEMM and its 2:4 form 3 times each and a 1 GiB device copy "
@@ -664,9 +708,14 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     M = N = K = args.size
-    if args.ace_only or args.ubench_only:
-        res = bench_ace(lib, stream) if args.ace_only else bench_ubench(lib, stream)
-        print(json.dumps({"ace" if args.ace_only else "ubench": res}), flush=True)
+    if args.ace_only or args.ubench_only or args.mixed_only:
+        if args.ace_only:
+            res = {"ace": bench_ace(lib, stream)}
+        elif args.ubench_only:
+            res = {"ubench": bench_ubench(lib, stream)}
+        else:
+            res = {"mixed": bench_mixed(lib, stream)}
+        print(json.dumps(res), flush=True)
         return
     if args.traffic_probe:
         xa, xb, qa, da, qb, db = make_operands(lib, M, N, K, 0)
@@ -754,6 +803,9 @@ def main():
         torch.cuda.empty_cache()
         log("concurrent streams (512^3) ...")
         extra["ace"] = bench_ace(lib, stream)
+        torch.cuda.empty_cache()
+        log("mixed-precision chains ...")
+        extra["mixed"] = bench_mixed(lib, stream)
         torch.cuda.empty_cache()
         log("served stream ...")
         if args.served_sweep:

@@ -49,7 +49,8 @@ typedef enum {
 } fp8_status;
 
 typedef enum { FP8_E4M3 = 0, FP8_E5M2 = 1 } fp8_fmt;
-typedef enum { FP8_OUT_F32 = 0, FP8_OUT_BF16 = 1 } fp8_out;
+/* Output types (BF16 and FP16 rounded to nearest even). */
+typedef enum { FP8_OUT_F32 = 0, FP8_OUT_BF16 = 1, FP8_OUT_F16 = 2 } fp8_out;
 /* TENSOR: one scale.  ROW: one per row of A (M values) / per column of B (N values). */
 typedef enum { FP8_SCALE_TENSOR = 0, FP8_SCALE_ROW = 1 } fp8_scale_kind;
 /* Which operand is 2:4-compressed.  A: the M x K activations; B: the weight,
@@ -222,6 +223,94 @@ fp8_status fp8_sparse24_both_gemm_workspace_size(const fp8_sparse24_both_gemm_ar
                                                  size_t *bytes);
 fp8_status fp8_sparse24_both_gemm(const fp8_sparse24_both_gemm_args *args, const fp8_plan *plan, void *ws,
                                   size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Higher-precision GEMMs (the FP32 and 16-bit stages of Sec. 8.3).          */
+/* ------------------------------------------------------------------------ */
+/* The mixed-precision sequence of Sec. 8.3 runs FP32 and 16-bit matrix
+ * operations beside the FP8 ones.  C = diag(s_a) (A x B) diag(s_b) with
+ *   a: row-major M x K, b: N rows of K (column-major K x N), both of type
+ *      ab_type (FP32 on the FP32 MFMA, FP16 / BF16 on the 16-bit MFMA with
+ *      exact products and FP32 sums); lda, ldb, ldc count elements
+ *   a_scale: 1 or M floats, b_scale: 1 or N floats (device)
+ *   c: row-major M x N, FP32, BF16 or FP16 (RNE), computed as
+ *      (acc * s_a[i]) * s_b[j] in FP32.
+ * The result is within 4 K 2^-24 sum |a b s_a s_b| of the exact one (plus the
+ * output rounding).  Requirements: K <= 2^20, a and b 16-byte aligned with
+ * 16-byte row strides.  Errors: FP8_ERR_ARG, FP8_ERR_SHAPE, FP8_ERR_ALIGN;
+ * nothing is enqueued on error.  Asynchronous on `stream`. */
+typedef enum { FP8_HP_F32 = 0, FP8_HP_F16 = 1, FP8_HP_BF16 = 2 } fp8_hp_type;
+typedef struct {
+    int64_t M, N, K;
+    const void *a; int64_t lda;
+    const void *b; int64_t ldb;
+    fp8_hp_type ab_type;
+    const float *a_scale; fp8_scale_kind a_kind;
+    const float *b_scale; fp8_scale_kind b_kind;
+    void *c; fp8_out c_type; int64_t ldc;
+} fp8_hp_gemm_args;
+fp8_status fp8_hp_gemm(const fp8_hp_gemm_args *args, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Mixed-precision sequences and their co-scheduling (Sec. 8.3, Sec. 9.2).   */
+/* ------------------------------------------------------------------------ */
+/* The mixed-precision workload of Sec. 8.3 is a sequence of matrix
+ * operations in different precisions; Sec. 9.2 advises co-scheduling
+ * kernels of similar wavefront needs and co-locating memory-bound FP8 work
+ * with compute-bound FP32 work.  A chain is a sequence of GEMM stages
+ * Y_s = X_s W_s^T over M rows, stage s in its own precision; its K is the
+ * previous stage's N (stage 0: in_width).  Stage s writes its result in the
+ * input type of stage s + 1 (FP32, FP16 or BF16, rounded to nearest even by
+ * the GEMM epilogue; FP32 for an FP8 stage, which quantizes its input per
+ * row to E4M3 with fp8_quantize before its fp8_gemm).  The last stage writes
+ * FP32.  n_chains independent chains share the weights.
+ *   w: N x K weight rows in the stage's type, leading dimension K, 16-byte
+ *      aligned (FP8: E4M3 codes)
+ *   w_scale: FP8 stage: N descales (or NULL = 1); other stages: NULL = 1, or
+ *            N column scales
+ * Stage widths must give 16-byte rows (K a multiple of 16 for FP8 stages).
+ * fp8_chain_create allocates every activation buffer, the FP8 staging and
+ * split-K workspace of each chain, max_streams (1..8) streams of default
+ * priority and the timing events; fp8_chain_destroy frees them (after
+ * draining).  fp8_chain_buffer gives stage s's input buffer of a chain
+ * (row-major M x K_s, leading dimension *ld elements; stage = n_stages gives
+ * the FP32 output) - the caller fills stage 0's input before fp8_chain_run.
+ * fp8_chain_run synchronizes the device, enqueues every chain under the
+ * schedule and waits for the end:
+ *   SERIAL    one stream, chain after chain;
+ *   IN_PHASE  chain c on stream c % n_streams, all streams starting together
+ *             (the stages that overlap share a precision);
+ *   STAGGERED as IN_PHASE, but stream k starts once stream k - 1 has finished
+ *             its first stage (neighbouring streams overlap different
+ *             precisions).
+ * Results do not depend on the schedule (same kernels and plans).  Stats:
+ * makespan, per-precision mean and coefficient of variation of the stage
+ * times (each stage bracketed by events on its stream: the span its kernels
+ * took, contention included; an FP8 stage includes its quantize) and
+ * aggregate TFLOP/s (2 M N K per stage).  fp8_chain_stage_ms gives one
+ * stage's time of the last run. */
+typedef enum { FP8_STAGE_F32 = 0, FP8_STAGE_F16 = 1, FP8_STAGE_BF16 = 2, FP8_STAGE_FP8 = 3 } fp8_stage_prec;
+typedef enum { FP8_CHAIN_SERIAL = 0, FP8_CHAIN_IN_PHASE = 1, FP8_CHAIN_STAGGERED = 2 } fp8_chain_schedule;
+typedef struct {
+    int precision;            /* fp8_stage_prec */
+    int64_t N;
+    const void *w;
+    const float *w_scale;
+} fp8_chain_stage;
+typedef struct {
+    double makespan_ms;
+    double stage_ms_mean[4];  /* indexed by fp8_stage_prec */
+    double stage_ms_cv[4];
+    int stage_count[4];
+    double tflops;
+} fp8_chain_stats;
+typedef struct fp8_chain fp8_chain;
+fp8_status fp8_chain_create(const fp8_chain_stage *stages, int n_stages, int64_t M, int64_t in_width, int n_chains,
+                            int max_streams, fp8_chain **out);
+fp8_status fp8_chain_buffer(fp8_chain *chain, int chain_index, int stage, void **ptr, int64_t *ld);
+fp8_status fp8_chain_run(fp8_chain *chain, int schedule, int n_streams, fp8_chain_stats *stats);
+fp8_status fp8_chain_stage_ms(fp8_chain *chain, int chain_index, int stage, double *ms);
+fp8_status fp8_chain_destroy(fp8_chain *chain);
 
 /* ------------------------------------------------------------------------ */
 /* Autotuner.                                                                */

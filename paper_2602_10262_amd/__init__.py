@@ -15,7 +15,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfp8gemm.so")
 
 FP8_E4M3, FP8_E5M2 = 0, 1
-FP8_OUT_F32, FP8_OUT_BF16 = 0, 1
+FP8_OUT_F32, FP8_OUT_BF16, FP8_OUT_F16 = 0, 1, 2
+FP8_HP_F32, FP8_HP_F16, FP8_HP_BF16 = 0, 1, 2
+FP8_STAGE_F32, FP8_STAGE_F16, FP8_STAGE_BF16, FP8_STAGE_FP8 = 0, 1, 2, 3
+FP8_CHAIN_SERIAL, FP8_CHAIN_IN_PHASE, FP8_CHAIN_STAGGERED = 0, 1, 2
 FP8_SCALE_TENSOR, FP8_SCALE_ROW = 0, 1
 FP8_SPARSE_A, FP8_SPARSE_B = 0, 1
 STATUS = ["FP8_OK", "FP8_ERR_ARG", "FP8_ERR_SHAPE", "FP8_ERR_ALIGN", "FP8_ERR_UNSUPPORTED", "FP8_ERR_HIP",
@@ -44,6 +47,21 @@ class Sparse24GemmArgs(ctypes.Structure):
 
 class Sparse24BothGemmArgs(ctypes.Structure):
     _fields_ = [("g", GemmArgs), ("a_values", _P), ("a_meta", _P), ("b_values", _P), ("b_meta", _P)]
+
+
+class HpGemmArgs(ctypes.Structure):
+    _fields_ = [("M", _I64), ("N", _I64), ("K", _I64), ("a", _P), ("lda", _I64), ("b", _P), ("ldb", _I64),
+                ("ab_type", _I), ("a_scale", _P), ("a_kind", _I), ("b_scale", _P), ("b_kind", _I),
+                ("c", _P), ("c_type", _I), ("ldc", _I64)]
+
+
+class ChainStage(ctypes.Structure):
+    _fields_ = [("precision", _I), ("N", _I64), ("w", _P), ("w_scale", _P)]
+
+
+class ChainStats(ctypes.Structure):
+    _fields_ = [("makespan_ms", _D), ("stage_ms_mean", _D * 4), ("stage_ms_cv", _D * 4), ("stage_count", _I * 4),
+                ("tflops", _D)]
 
 
 class GroupProblem(ctypes.Structure):
@@ -99,6 +117,12 @@ _SIGS = {
     "fp8_ubench_mfma": [_I, _I, _I, _I, _P, _P],
     "fp8_ubench_lds": [_I, _I, _P, _P],
     "fp8_ubench_lds_pattern": [_I, _I, _I, _P, _P],
+    "fp8_hp_gemm": [_P, _P],
+    "fp8_chain_create": [_P, _I, _I64, _I64, _I, _I, _P],
+    "fp8_chain_buffer": [_P, _I, _I, _P, _P],
+    "fp8_chain_run": [_P, _I, _I, _P],
+    "fp8_chain_stage_ms": [_P, _I, _I, _P],
+    "fp8_chain_destroy": [_P],
     "fp8_sparse24_both_gemm_plan_resolve": [_P, _P, _P],
     "fp8_sparse24_both_gemm_workspace_size": [_P, _P, _P],
     "fp8_sparse24_both_gemm": [_P, _P, _P, _SZ, _P],
@@ -177,6 +201,11 @@ def _u8(t):
     return t.view(torch.uint8) if t.dtype != torch.uint8 else t
 
 
+def _out_type(dtype) -> int:
+    import torch
+    return {torch.bfloat16: FP8_OUT_BF16, torch.float16: FP8_OUT_F16}.get(dtype, FP8_OUT_F32)
+
+
 # ---------------------------------------------------------------- quantize --
 
 def fp8_quantize(x, fmt: int = FP8_E4M3, kind: int = FP8_SCALE_TENSOR, q=None, scale=None, descale=None,
@@ -201,7 +230,7 @@ def fp8_quantize(x, fmt: int = FP8_E4M3, kind: int = FP8_SCALE_TENSOR, q=None, s
 def gemm_args(a, b_nk, a_descale, b_descale, c, a_fmt=FP8_E4M3, b_fmt=FP8_E4M3, c_type=None,
               M=None, N=None, K=None) -> GemmArgs:
     import torch
-    c_type = (FP8_OUT_BF16 if c.dtype == torch.bfloat16 else FP8_OUT_F32) if c_type is None else c_type
+    c_type = _out_type(c.dtype) if c_type is None else c_type
     M = M if M is not None else (a.shape[0] if a is not None else c.shape[0])
     N = N if N is not None else (b_nk.shape[0] if b_nk is not None else c.shape[1])
     K = K if K is not None else (a.shape[1] if a is not None else b_nk.shape[1])
@@ -387,6 +416,99 @@ def fp8_sparse24_both_gemm_plan_resolve(args, plan=None):
     return res.tile, res.split_k
 
 
+# ------------------------------------------------ higher-precision GEMM ----
+
+def fp8_hp_gemm(a, b_nk, a_scale=None, b_scale=None, out_dtype=None, c=None, stream=None):
+    """C = diag(s_a) A B diag(s_b) for FP32, FP16 or BF16 tensors A (M x K) and
+    B given as N x K rows; scales: None (1), one float or M / N floats."""
+    import torch
+    types = {torch.float32: FP8_HP_F32, torch.float16: FP8_HP_F16, torch.bfloat16: FP8_HP_BF16}
+    if a.dtype != b_nk.dtype or a.dtype not in types:
+        raise ValueError("A and B must share one of float32, float16, bfloat16")
+    M, K = a.shape
+    N = b_nk.shape[0]
+    one = None
+    if a_scale is None or b_scale is None:
+        one = torch.ones(1, dtype=torch.float32, device=a.device)
+    a_scale = one if a_scale is None else a_scale
+    b_scale = one if b_scale is None else b_scale
+    if c is None:
+        c = torch.empty((M, N), dtype=out_dtype or torch.float32, device=a.device)
+    args = HpGemmArgs(M, N, K, a.data_ptr(), a.stride(0), b_nk.data_ptr(), b_nk.stride(0), types[a.dtype],
+                      a_scale.data_ptr(), FP8_SCALE_ROW if a_scale.numel() > 1 else FP8_SCALE_TENSOR,
+                      b_scale.data_ptr(), FP8_SCALE_ROW if b_scale.numel() > 1 else FP8_SCALE_TENSOR,
+                      c.data_ptr(), _out_type(c.dtype), c.stride(0))
+    _call("fp8_hp_gemm", ctypes.byref(args), _stream(stream))
+    return c
+
+
+class Chain:
+    """Mixed-precision GEMM chains (fp8_chain_*): stages = [(precision, weight
+    tensor N x K, w_scale tensor or None)], M rows, in_width columns of input."""
+
+    def __init__(self, stages, M: int, in_width: int, n_chains: int, max_streams: int = 4):
+        if any(not w.is_contiguous() for _, w, _ in stages):
+            raise ValueError("chain weights must be contiguous N x K tensors")
+        self._keep = [(w, sc) for _, w, sc in stages]
+        arr = (ChainStage * len(stages))(*[ChainStage(p, w.shape[0], w.data_ptr(), _ptr(sc)) for p, w, sc in stages])
+        self.stages = stages
+        self.n_chains = n_chains
+        self.M = M
+        self._h = ctypes.c_void_p()
+        _call("fp8_chain_create", arr, len(stages), M, in_width, n_chains, max_streams, ctypes.byref(self._h))
+
+    def buffer(self, chain: int, stage: int):
+        """(device pointer, leading dimension) of a stage's input (stage =
+        len(stages): the FP32 output)."""
+        ptr = ctypes.c_void_p()
+        ld = ctypes.c_int64()
+        _call("fp8_chain_buffer", self._h, chain, stage, ctypes.byref(ptr), ctypes.byref(ld))
+        return ptr.value, ld.value
+
+    def run(self, schedule: int, n_streams: int = 1) -> dict:
+        st = ChainStats()
+        _call("fp8_chain_run", self._h, schedule, n_streams, ctypes.byref(st))
+        names = ("f32", "f16", "bf16", "fp8")
+        return {"makespan_ms": st.makespan_ms, "tflops": st.tflops,
+                "stage_ms_mean": {names[p]: st.stage_ms_mean[p] for p in range(4) if st.stage_count[p]},
+                "stage_ms_cv": {names[p]: st.stage_ms_cv[p] for p in range(4) if st.stage_count[p]},
+                "stage_count": {names[p]: st.stage_count[p] for p in range(4) if st.stage_count[p]}}
+
+    def tensor(self, chain: int, stage: int):
+        """A torch view (no copy) of a stage's input buffer (stage =
+        len(stages): the FP32 output), through the CUDA array interface."""
+        import torch
+        ptr, ld = self.buffer(chain, stage)
+        if stage == len(self.stages):
+            typestr, dtype = "<f4", torch.float32
+        else:
+            prec = self.stages[stage][0]
+            typestr, dtype = {FP8_STAGE_F32: ("<f4", torch.float32), FP8_STAGE_FP8: ("<f4", torch.float32),
+                              FP8_STAGE_F16: ("<f2", torch.float16), FP8_STAGE_BF16: ("<i2", torch.bfloat16)}[prec]
+
+        class _View:
+            __cuda_array_interface__ = {"shape": (self.M, ld), "typestr": typestr, "data": (ptr, False),
+                                        "version": 2, "strides": None}
+        t = torch.as_tensor(_View(), device="cuda")
+        return t.view(dtype) if dtype == torch.bfloat16 else t
+
+    def stage_ms(self, chain: int, stage: int) -> float:
+        ms = ctypes.c_double()
+        _call("fp8_chain_stage_ms", self._h, chain, stage, ctypes.byref(ms))
+        return ms.value
+
+    def close(self):
+        if self._h:
+            _call("fp8_chain_destroy", self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ----------------------------------------------------------------- tuning ---
 
 def fp8_tune_gemm(args: GemmArgs, iters: int = 10, stream=None):
@@ -498,7 +620,7 @@ def fp8_validate(c, cref, sabs, K, stream=None) -> dict:
     import torch
     M, N = c.shape
     out = torch.empty(5, dtype=torch.float64, device=c.device)
-    c_type = FP8_OUT_BF16 if c.dtype == torch.bfloat16 else FP8_OUT_F32
+    c_type = _out_type(c.dtype)
     _call("fp8_validate", c.data_ptr(), c_type, c.stride(0), cref.data_ptr(), sabs.data_ptr(), M, N, K,
           out.data_ptr(), _stream(stream))
     o = out.cpu().tolist()

@@ -43,7 +43,8 @@ static fp8_status check_common(const fp8_gemm_args *a, bool need_a, bool need_b)
         return set_error(FP8_ERR_SHAPE, "M, N, K must be in [1, 2^30]");
     if ((int64_t)a->M * a->N > ((int64_t)1 << 40)) return set_error(FP8_ERR_SHAPE, "M*N too large");
     if (!fmt_ok(a->a_fmt) || !fmt_ok(a->b_fmt)) return set_error(FP8_ERR_ARG, "unknown FP8 format");
-    if (a->c_type != FP8_OUT_F32 && a->c_type != FP8_OUT_BF16) return set_error(FP8_ERR_ARG, "unknown output type");
+    if (a->c_type != FP8_OUT_F32 && a->c_type != FP8_OUT_BF16 && a->c_type != FP8_OUT_F16)
+        return set_error(FP8_ERR_ARG, "unknown output type");
     if ((a->a_kind != FP8_SCALE_TENSOR && a->a_kind != FP8_SCALE_ROW) ||
         (a->b_kind != FP8_SCALE_TENSOR && a->b_kind != FP8_SCALE_ROW))
         return set_error(FP8_ERR_ARG, "unknown scale kind");
@@ -74,11 +75,11 @@ fp8_status prepare_dense(const fp8_gemm_args *a, Prepared &out)
     p.b = a->b; p.ldb = a->ldb;
     p.si = a->a_descale; p.si_per = a->a_kind == FP8_SCALE_ROW;
     p.sj = a->b_descale; p.sj_per = a->b_kind == FP8_SCALE_ROW;
-    p.c = a->c; p.ldc = a->ldc; p.out_bf16 = a->c_type == FP8_OUT_BF16; p.trans_out = 0;
+    p.c = a->c; p.ldc = a->ldc; p.out_bf16 = a->c_type == FP8_OUT_BF16; p.out_f16 = a->c_type == FP8_OUT_F16; p.trans_out = 0;
     p.M = (int)a->M; p.N = (int)a->N; p.K = (int)a->K;
     p.splits = 1; p.kchunk = ((p.K + kBKHost - 1) / kBKHost) * kBKHost;
     out.fa = a->a_fmt; out.fb = a->b_fmt; out.sparse = false;
-    out.key = GemmKey{a->M, a->N, a->K, out.fa, out.fb, p.out_bf16, p.si_per, p.sj_per, 0};
+    out.key = GemmKey{a->M, a->N, a->K, out.fa, out.fb, (int)a->c_type, p.si_per, p.sj_per, 0};
     return FP8_OK;
 }
 
@@ -98,7 +99,7 @@ fp8_status prepare_sparse(const fp8_sparse24_gemm_args *s, Prepared &out)
     std::memset(&p, 0, sizeof(p));
     p.a = s->values; p.lda = a->K / 2;
     p.meta = s->meta; p.ldm = a->K / 8;
-    p.c = a->c; p.ldc = a->ldc; p.out_bf16 = a->c_type == FP8_OUT_BF16;
+    p.c = a->c; p.ldc = a->ldc; p.out_bf16 = a->c_type == FP8_OUT_BF16; p.out_f16 = a->c_type == FP8_OUT_F16;
     p.K = (int)a->K;
     p.splits = 1; p.kchunk = ((p.K + kBKHost - 1) / kBKHost) * kBKHost;
     if (side_a) {
@@ -116,7 +117,7 @@ fp8_status prepare_sparse(const fp8_sparse24_gemm_args *s, Prepared &out)
         out.fa = a->b_fmt; out.fb = a->a_fmt;
     }
     out.sparse = true;
-    out.key = GemmKey{p.M, p.N, a->K, out.fa, out.fb, p.out_bf16, p.si_per, p.sj_per, side_a ? 1 : 2};
+    out.key = GemmKey{p.M, p.N, a->K, out.fa, out.fb, (int)a->c_type, p.si_per, p.sj_per, side_a ? 1 : 2};
     return FP8_OK;
 }
 
@@ -402,7 +403,7 @@ static fp8_status prepare_both(const fp8_sparse24_both_gemm_args *s, Prepared &o
     std::memset(&p, 0, sizeof(p));
     p.lda = p.ldb = a->K / 2;
     p.ldm = p.ldmb = a->K / 8;
-    p.c = a->c; p.ldc = a->ldc; p.out_bf16 = a->c_type == FP8_OUT_BF16;
+    p.c = a->c; p.ldc = a->ldc; p.out_bf16 = a->c_type == FP8_OUT_BF16; p.out_f16 = a->c_type == FP8_OUT_F16;
     p.K = (int)a->K;
     p.splits = 1; p.kchunk = ((p.K + kBKHost - 1) / kBKHost) * kBKHost;
     if (!swap) {
@@ -421,7 +422,7 @@ static fp8_status prepare_both(const fp8_sparse24_both_gemm_args *s, Prepared &o
         out.fa = a->b_fmt; out.fb = a->a_fmt;
     }
     out.sparse = true;
-    out.key = GemmKey{p.M, p.N, a->K, out.fa, out.fb, p.out_bf16, p.si_per, p.sj_per, 3};
+    out.key = GemmKey{p.M, p.N, a->K, out.fa, out.fb, (int)a->c_type, p.si_per, p.sj_per, 3};
     return FP8_OK;
 }
 

@@ -17,7 +17,7 @@ void clear_error();
 // Everything that identifies a GEMM for plan choice and for the tuning cache.
 struct GemmKey {
     int64_t mk, nk, kk;       // kernel-view dimensions: i count, j count, K
-    int fa, fb, out_bf16, si_per, sj_per, sparse;
+    int fa, fb, out_type, si_per, sj_per, sparse;   // out_type: fp8_out
 };
 
 // Kernel-view parameters of a dense or sparse call after argument checking.

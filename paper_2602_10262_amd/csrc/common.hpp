@@ -82,6 +82,16 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
     return (uint16_t)(u >> 16);
 }
 
+// FP32 -> FP16 bits, round to nearest even (the hardware conversion),
+// overflow to infinity, NaN kept.
+__device__ __forceinline__ uint16_t f32_to_f16_rne(float x)
+{
+    const _Float16 h = (_Float16)x;
+    uint16_t u;
+    __builtin_memcpy(&u, &h, 2);
+    return u;
+}
+
 // wave64 reductions through cross-lane shuffles
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 {

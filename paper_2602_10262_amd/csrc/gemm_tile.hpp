@@ -156,6 +156,7 @@ __device__ __forceinline__ void store_out(const GemmParams &p, int i, int j, flo
     float v = p.trans_out ? (acc * sj) * si : (acc * si) * sj;
     int64_t off = p.trans_out ? (int64_t)j * p.ldc + i : (int64_t)i * p.ldc + j;
     if (p.out_bf16) reinterpret_cast<uint16_t *>(p.c)[off] = f32_to_bf16_rne(v);
+    else if (p.out_f16) reinterpret_cast<uint16_t *>(p.c)[off] = f32_to_f16_rne(v);
     else reinterpret_cast<float *>(p.c)[off] = v;
 }
 
@@ -198,16 +199,19 @@ __device__ __forceinline__ void store4(const GemmParams &p, int i, int j, int sp
         }
         const int64_t off = (int64_t)row * p.ldc + col0;
         const bool vec = col0 + 3 < cols && (p.ldc % 4) == 0 && ((reinterpret_cast<uintptr_t>(p.c) & 15) == 0);
-        if (p.out_bf16) {
+        if (p.out_bf16 || p.out_f16) {
             uint16_t *c = reinterpret_cast<uint16_t *>(p.c) + off;
+            uint16_t h[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) h[q] = p.out_bf16 ? f32_to_bf16_rne(o[q]) : f32_to_f16_rne(o[q]);
             if (vec) {
                 uint2 w;
-                w.x = (uint32_t)f32_to_bf16_rne(o[0]) | ((uint32_t)f32_to_bf16_rne(o[1]) << 16);
-                w.y = (uint32_t)f32_to_bf16_rne(o[2]) | ((uint32_t)f32_to_bf16_rne(o[3]) << 16);
+                w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+                w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
                 *reinterpret_cast<uint2 *>(c) = w;
             } else {
                 for (int q = 0; q < 4; ++q)
-                    if (col0 + q < cols) c[q] = f32_to_bf16_rne(o[q]);
+                    if (col0 + q < cols) c[q] = h[q];
             }
         } else {
             float *c = reinterpret_cast<float *>(p.c) + off;
@@ -245,7 +249,8 @@ __device__ __forceinline__ void write_tile_staged(const GemmParams &p, const v4f
     constexpr int RQ = ROW_PER_Q ? 4 : 1;
     const int wm = wave / WN, wn = wave % WN;
     const int lr = lane & 15, lg = lane >> 4;
-    const bool bf = p.out_bf16 != 0;
+    const bool bf = p.out_bf16 != 0 || p.out_f16 != 0;   // 16-bit output
+    const bool f16 = p.out_f16 != 0 && p.out_bf16 == 0;
     const int esz = bf ? 2 : 4;
     const int per = bf ? 8 : 4;                                 // output elements per 16-byte chunk
     const int chunks_row = OC / per;                            // divides 64: a lane's chunk column is fixed
@@ -317,7 +322,7 @@ __device__ __forceinline__ void write_tile_staged(const GemmParams &p, const v4f
                 v[4] = x1.x * cd[4]; v[5] = x1.y * cd[5]; v[6] = x1.z * cd[6]; v[7] = x1.w * cd[7];
                 uint16_t h[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) h[e] = f32_to_bf16_rne(v[e]);
+                for (int e = 0; e < 8; ++e) h[e] = f16 ? f32_to_f16_rne(v[e]) : f32_to_bf16_rne(v[e]);
                 if (full) {
                     *reinterpret_cast<uint4 *>(dst) = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16,
                                                                  h[4] | (uint32_t)h[5] << 16, h[6] | (uint32_t)h[7] << 16);
@@ -341,7 +346,7 @@ __device__ __forceinline__ void write_tile_staged(const GemmParams &p, const v4f
 // 8-byte pieces of sixteen rows that one MFMA result holds.  The value is
 // (acc * d_i) * d_j (transposed output: (acc * d_j) * d_i) in FP32: the
 // staged value carries the output row's descale, the column's is applied
-// when the row chunk is stored, as FP32 or as BF16 (RNE).  Split-K partial
+// when the row chunk is stored, as FP32, BF16 or FP16 (both RNE).  Split-K partial
 // sums go to the workspace through store4 instead.  Every wave of the
 // workgroup must call it (it synchronises the workgroup) once the main loop
 // no longer touches LDS.  LDS_BYTES: LDS the tile owns.

@@ -25,7 +25,8 @@ struct GemmParams {
     int64_t lda, ldm, ldb, ldc, ldmb;
     int M, N, K;
     int si_per, sj_per;    // 1: one descale per row / column
-    int out_bf16;
+    int out_bf16;          // BF16 output (RNE)
+    int out_f16;           // FP16 output (RNE); neither: FP32
     int trans_out;         // store transposed; descales then apply j first
     int splits;            // >= 1
     int kchunk;            // K range per split, a multiple of 128

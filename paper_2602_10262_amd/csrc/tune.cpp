@@ -49,12 +49,12 @@ int64_t pow2_ceil(int64_t v)
 
 KeyT make_key(const GemmKey &k)
 {
-    return KeyT{pow2_ceil(k.mk), pow2_ceil(k.nk), k.kk, k.fa, k.fb, k.out_bf16, k.si_per, k.sj_per, k.sparse};
+    return KeyT{pow2_ceil(k.mk), pow2_ceil(k.nk), k.kk, k.fa, k.fb, k.out_type, k.si_per, k.sj_per, k.sparse};
 }
 
-BeKeyT make_be_key(int64_t M, int64_t N, int64_t K, int side, int fa, int fb, int out_bf16)
+BeKeyT make_be_key(int64_t M, int64_t N, int64_t K, int side, int fa, int fb, int out_type)
 {
-    return BeKeyT{pow2_ceil(M), N, K, side, fa, fb, out_bf16};
+    return BeKeyT{pow2_ceil(M), N, K, side, fa, fb, out_type};
 }
 
 // Identity of the current device and runtime: "<arch> <product>" and the HIP
@@ -318,7 +318,7 @@ fp8_status fp8_tune_cache_save(const char *path)
         const KeyT &k = kv.first;
         std::fprintf(f,
                      "{\"kind\": \"plan\", \"device\": \"%s\", \"runtime\": %d, \"mk\": %lld, \"nk\": %lld, "
-                     "\"kk\": %lld, \"fa\": %d, \"fb\": %d, \"out_bf16\": %d, \"si_per\": %d, \"sj_per\": %d, "
+                     "\"kk\": %lld, \"fa\": %d, \"fb\": %d, \"out_type\": %d, \"si_per\": %d, \"sj_per\": %d, "
                      "\"sparse\": %d, \"tile\": %d, \"split_k\": %d, \"us\": %.3f}\n",
                      dev.c_str(), rt, (long long)std::get<0>(k), (long long)std::get<1>(k), (long long)std::get<2>(k),
                      std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k),
@@ -374,7 +374,7 @@ fp8_status fp8_tune_cache_load(const char *path)
         const std::string kind = kv.count("kind") ? kv["kind"] : "";
         if (kind == "plan") {
             const KeyT key{num(kv, "mk", ok), num(kv, "nk", ok), num(kv, "kk", ok), (int)num(kv, "fa", ok),
-                           (int)num(kv, "fb", ok), (int)num(kv, "out_bf16", ok), (int)num(kv, "si_per", ok),
+                           (int)num(kv, "fb", ok), (int)num(kv, "out_type", ok), (int)num(kv, "si_per", ok),
                            (int)num(kv, "sj_per", ok), (int)num(kv, "sparse", ok)};
             const int tile = (int)num(kv, "tile", ok), split = (int)num(kv, "split_k", ok);
             const double us = real(kv, "us", ok);

@@ -83,7 +83,7 @@ def test_tuning_cache_roundtrip(tmp_path):
     lib.fp8_tune_cache_clear()
     dev, rt = lib.fp8_tune_device_key()
     plan = {"kind": "plan", "device": dev, "runtime": rt, "mk": 8192, "nk": 8192, "kk": 8192, "fa": 0, "fb": 0,
-            "out_bf16": 1, "si_per": 1, "sj_per": 1, "sparse": 0, "tile": 3, "split_k": 2, "us": 123.0}
+            "out_type": 1, "si_per": 1, "sj_per": 1, "sparse": 0, "tile": 3, "split_k": 2, "us": 123.0}
     be = {"kind": "breakeven", "device": dev, "runtime": rt, "M": 16, "N": 8192, "K": 8192, "side": 1, "fa": 0,
           "fb": 0, "c_type": 1, "dense_us": 20.0, "sparse_us": 15.0, "dense_tile": 24, "dense_split": 1,
           "sparse_tile": 4, "sparse_split": 4, "use_sparse": 1}
