@@ -384,6 +384,110 @@ def bench_mixed(lib, stream, M=4096, H=2048, n_chains=8, streams=4):
     return res
 
 
+def bench_batching(lib, stream, batch_sizes=(4, 8, 16, 32), seeds=(0, 1, 2)):
+    """Should the server batch the requests it admits together into one
+    grouped launch?  For batches of B requests drawn from the served workload
+    (M log-uniform on [1, 8192], N and K from {2048, 4096, 8192, 14336}, half
+    with 2:4 weights), each request's activations are quantized per token and
+    multiplied by its weight, either (a) as the server does it: one quantize +
+    GEMM per request, requests spread round robin over 4 streams; or (b)
+    quantize per request on one stream, then one persistent grouped launch of
+    the batch (plan built beforehand; its host-side build time is reported
+    apart)."""
+    import ctypes
+    import torch
+    from paper_2602_10262_amd import synth
+    sizes = [2048, 4096, 8192, 14336]
+    L = lib.load()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    weights = {}
+
+    def weight(N, K, sp):
+        key = (N, K, sp)
+        if key not in weights:
+            w = torch.randn((N, K), device="cuda")
+            qw, _, dw = lib.fp8_quantize(w, 0, lib.FP8_SCALE_ROW)
+            del w
+            if sp:
+                v, m, _ = lib.fp8_sparse24_prune_compress(qw, 0, with_mask=False)
+                weights[key] = (v, m, dw)
+            else:
+                weights[key] = (qw, None, dw)
+        return weights[key]
+
+    out = []
+    for B in batch_sizes:
+        row = {"batch": B, "per_request_4_streams_ms": [], "grouped_ms": [], "plan_build_us": []}
+        for seed in seeds:
+            rng = np.random.default_rng(1000 * B + seed)
+            gen = torch.Generator(device="cuda").manual_seed(1000 * B + seed)
+            Ms = synth.log_uniform_int(rng, 1, 8192, B)
+            reqs = []
+            for i in range(B):
+                M, N, K = int(Ms[i]), int(rng.choice(sizes)), int(rng.choice(sizes))
+                sp = bool(rng.integers(0, 2))
+                x = torch.rand((M, K), device="cuda", generator=gen) * 2.0 - 1.0
+                q = torch.empty((M, K), dtype=torch.uint8, device="cuda")
+                sc = torch.empty(M, dtype=torch.float32, device="cuda")
+                dc = torch.empty(M, dtype=torch.float32, device="cuda")
+                c = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+                w, meta, dw = weight(N, K, sp)
+                if sp:
+                    args = lib.sparse24_args(w, meta, q, lib.FP8_SPARSE_B, dc, dw, c)
+                    ws, nb = lib._workspace("fp8_sparse24_gemm_workspace_size", ctypes.byref(args), None, "cuda")
+                    prob = lib.sparse_weight_problem(q, w, meta, dc, dw, c)
+                    fn = L.fp8_sparse24_gemm
+                else:
+                    args = lib.gemm_args(q, w, dc, dw, c)
+                    ws, nb = lib._workspace("fp8_gemm_workspace_size", ctypes.byref(args), None, "cuda")
+                    prob = lib.dense_problem(q, w, dc, dw, c)
+                    fn = L.fp8_gemm
+                reqs.append((x, q, sc, dc, c, args, ws, nb, fn, prob))
+            torch.cuda.synchronize()
+
+            def per_request():
+                for i, (x, q, sc, dc, c, args, ws, nb, fn, _) in enumerate(reqs):
+                    st = streams[i % 4]
+                    lib.fp8_quantize(x, 0, lib.FP8_SCALE_ROW, q=q, scale=sc, descale=dc, stream=st)
+                    fn(ctypes.byref(args), None, None if ws is None else ws.data_ptr(), nb, st.cuda_stream)
+
+            def span(fn_issue):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for st in streams:
+                    st.wait_event(e0)
+                fn_issue()
+                ends = []
+                for st in streams:
+                    e = torch.cuda.Event(enable_timing=True)
+                    e.record(st)
+                    ends.append(e)
+                torch.cuda.synchronize()
+                return max(e0.elapsed_time(e) for e in ends)
+
+            t0 = time.perf_counter()
+            plan = lib.GroupedPlan([r[9] for r in reqs], use_graph=True)
+            row["plan_build_us"].append((time.perf_counter() - t0) * 1e6)
+
+            def grouped():
+                st = streams[0]
+                for (x, q, sc, dc, *_r) in reqs:
+                    lib.fp8_quantize(x, 0, lib.FP8_SCALE_ROW, q=q, scale=sc, descale=dc, stream=st)
+                plan.run(st)
+
+            span(per_request)
+            span(grouped)
+            row["per_request_4_streams_ms"].append(min(span(per_request) for _ in range(3)))
+            row["grouped_ms"].append(min(span(grouped) for _ in range(3)))
+            plan.close()
+            del reqs
+        row["per_request_median_ms"] = float(np.median(row["per_request_4_streams_ms"]))
+        row["grouped_median_ms"] = float(np.median(row["grouped_ms"]))
+        row["grouped_speedup"] = row["per_request_median_ms"] / row["grouped_median_ms"]
+        out.append(row)
+    return out
+
+
 def bench_encode(lib, stream, sizes=(256, 512, 2048, 8192)):
     """The 2:4 encode step (the overhead the paper measures apart from the
     GEMM): FP32 -> codes -> pruned and compressed, per-row scales, as two
@@ -662,11 +766,30 @@ def bench_ubench(lib, stream):
         ms = lib.fp8_ubench_lds(waves, 4096, stream)
         nbytes = cus * waves * 64 * 16 * 4096
         out["lds"].append({"waves_per_cu": waves, "tbs": nbytes / (ms * 1e-3) / 1e12})
+    # every swizzle of a compressed (64-byte) row that XORs row bits into the
+    # chunk index, on the compressed-fragment read: time relative to a linear
+    # read of the same bytes (about 1: conflict-free, about 1.7: 2-way)
+    lin = [16 * l for l in range(64)]
+    lib.fp8_ubench_lds_offsets(lin, 8, 16, stream)
+    t_lin = min(lib.fp8_ubench_lds_offsets(lin, 8, 2048, stream) for _ in range(3))
+    sweep = {}
+    for m0 in range(16):
+        for m1 in range(16):
+            def h(r):
+                return (bin(m0 & r).count("1") & 1) | ((bin(m1 & r).count("1") & 1) << 1)
+            offs = [(l & 15) * 64 + (((l >> 4) ^ h(l & 15)) << 4) for l in range(64)]
+            sweep[(m0, m1)] = min(lib.fp8_ubench_lds_offsets(offs, 8, 2048, stream) for _ in range(2)) / t_lin
+    vals = sorted(sweep.values())
+    out["compressed_swizzle_sweep"] = {
+        "candidates": len(vals), "conflict_free": sum(v < 1.3 for v in vals),
+        "two_way": sum(1.3 <= v < 2.5 for v in vals), "four_way": sum(v >= 2.5 for v in vals),
+        "library_swizzle_rel_time": sweep[(2, 8)], "previous_swizzle_rel_time": sweep[(10, 4)],
+        "unswizzled_rel_time": sweep[(0, 0)]}
     # the address patterns of the GEMM fragment reads, 8 waves per CU
     out["lds_patterns"] = []
     for pat, name in lib.LDS_PATTERNS.items():
         ms = lib.fp8_ubench_lds_pattern(pat, 8, 4096, stream)
-        per_lane = 4 if pat == 4 else 16
+        per_lane = {4: 4, 6: 8}.get(pat, 16)
         nbytes = cus * 8 * 64 * per_lane * 4096
         out["lds_patterns"].append({"pattern": name, "tbs": nbytes / (ms * 1e-3) / 1e12,
                                     "ns_per_instr_per_wave": ms * 1e6 / 4096})
@@ -689,6 +812,7 @@ def main():
     ap.add_argument("--ace-only", action="store_true", help="only the concurrent-stream study (for counter runs)")
     ap.add_argument("--ubench-only", action="store_true", help="only the matrix-core and LDS microbenchmarks")
     ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision GEMMs and chains")
+    ap.add_argument("--batching-only", action="store_true", help="only the per-request vs grouped batch study")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the headline GEMM and its 2:4 form 3 times each and a 1 GiB device copy "
@@ -708,8 +832,10 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     M = N = K = args.size
-    if args.ace_only or args.ubench_only or args.mixed_only:
-        if args.ace_only:
+    if args.ace_only or args.ubench_only or args.mixed_only or args.batching_only:
+        if args.batching_only:
+            res = {"batching": bench_batching(lib, stream)}
+        elif args.ace_only:
             res = {"ace": bench_ace(lib, stream)}
         elif args.ubench_only:
             res = {"ubench": bench_ubench(lib, stream)}
@@ -806,6 +932,9 @@ def main():
         torch.cuda.empty_cache()
         log("mixed-precision chains ...")
         extra["mixed"] = bench_mixed(lib, stream)
+        torch.cuda.empty_cache()
+        log("batching admitted requests ...")
+        extra["batching"] = bench_batching(lib, stream)
         torch.cuda.empty_cache()
         log("served stream ...")
         if args.served_sweep:

@@ -499,14 +499,22 @@ fp8_status fp8_server_destroy(fp8_server *srv);                               /*
  * fragment read (lane l reads row l % 16 of a 16-row block at chunk position
  * l / 16; each iteration moves to the next block): 0 linear (= fp8_ubench_lds),
  * 1 dense operand (128-byte swizzled rows, 16 bytes at chunk 2 (l/16)),
- * 2 compressed operand (64-byte swizzled rows), 3 dense operand at the 2:4 B
- * chunk positions, 4 metadata (16-byte rows, 4 bytes per lane: ds_read_b32),
- * 5 compressed operand without swizzle.  Bank conflicts of a pattern appear
- * as a longer time (and in the LDS conflict counters).  Patterns outside 0..5
- * are rejected with FP8_ERR_ARG. */
+ * 2 compressed operand (64-byte swizzled rows), 3 dense B operand of the 2:4
+ * kernels at its chunk positions (l/16 + 4) and swizzle, 4 metadata (16-byte
+ * rows, 4 bytes per lane: ds_read_b32), 5 compressed operand without swizzle,
+ * 6 metadata of two 16-row blocks in one instruction (8 bytes per lane,
+ * ds_read2st64_b32), 7 the read of 3 on the dense kernels' swizzle.  Bank
+ * conflicts of a pattern appear as a longer time (and in the LDS conflict
+ * counters).  Patterns outside 0..7 are rejected with FP8_ERR_ARG. */
 fp8_status fp8_ubench_mfma(int kind, int waves_per_cu, int chains, int iters, void *stream, double *ms);
 fp8_status fp8_ubench_lds(int waves_per_cu, int iters, void *stream, double *ms);
 fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void *stream, double *ms);
+/* Any 128-bit read pattern: lane l of every wave reads 16 bytes at
+ * lane_offsets[l] (64 host ints, 16-byte aligned, below 32768) plus a
+ * per-iteration shift of a multiple of 2 KiB; times as above.  A lane pattern
+ * whose reads collide in a bank takes longer, so lane groupings and bank
+ * mappings can be probed.  FP8_ERR_ARG for offsets outside that range. */
+fp8_status fp8_ubench_lds_offsets(const int *lane_offsets, int waves_per_cu, int iters, void *stream, double *ms);
 
 /* ------------------------------------------------------------------------ */
 /* Validator support: FP64 error norms on the device.                        */

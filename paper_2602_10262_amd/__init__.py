@@ -117,6 +117,7 @@ _SIGS = {
     "fp8_ubench_mfma": [_I, _I, _I, _I, _P, _P],
     "fp8_ubench_lds": [_I, _I, _P, _P],
     "fp8_ubench_lds_pattern": [_I, _I, _I, _P, _P],
+    "fp8_ubench_lds_offsets": [_P, _I, _I, _P, _P],
     "fp8_hp_gemm": [_P, _P],
     "fp8_chain_create": [_P, _I, _I64, _I64, _I, _I, _P],
     "fp8_chain_buffer": [_P, _I, _I, _P, _P],
@@ -603,13 +604,21 @@ def fp8_ubench_lds(waves_per_cu: int, iters: int, stream=None) -> float:
     return ms.value
 
 
-LDS_PATTERNS = {0: "linear", 1: "dense_fragment", 2: "compressed_fragment", 3: "dense_at_2to4_b_chunks",
-                4: "metadata_b32", 5: "compressed_unswizzled"}
+LDS_PATTERNS = {0: "linear", 1: "dense_fragment", 2: "compressed_fragment", 3: "2to4_b_operand",
+                4: "metadata_b32", 5: "compressed_unswizzled", 6: "metadata_pair_read2st64",
+                7: "2to4_b_chunks_on_dense_swizzle"}
 
 
 def fp8_ubench_lds_pattern(pattern: int, waves_per_cu: int, iters: int, stream=None) -> float:
     ms = ctypes.c_double(0)
     _call("fp8_ubench_lds_pattern", pattern, waves_per_cu, iters, _stream(stream), ctypes.byref(ms))
+    return ms.value
+
+
+def fp8_ubench_lds_offsets(lane_offsets, waves_per_cu: int, iters: int, stream=None) -> float:
+    arr = (ctypes.c_int * 64)(*[int(o) for o in lane_offsets])
+    ms = ctypes.c_double(0)
+    _call("fp8_ubench_lds_offsets", arr, waves_per_cu, iters, _stream(stream), ctypes.byref(ms))
     return ms.value
 
 

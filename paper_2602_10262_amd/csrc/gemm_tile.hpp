@@ -111,17 +111,35 @@ constexpr bool tile_dense_fits(int bm, int bn, int pf)
                ((pf == kExactPF ? 256 : 128) * (bm + bn)) <= kMaxLdsBytes;
 }
 
-// Compressed rows (64 value bytes) keep their 16-byte chunk c at c ^ h(r),
-// h(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1): the 16 rows a fragment read touches
-// land on 16 different 16-byte bank groups (and any 8 consecutive rows on 8).
-__device__ __forceinline__ int swz_sp(int r, int c) { return r * 64 + ((c ^ ((r >> 1) & 3) ^ ((r >> 3) & 1)) << 4); }
+// LDS swizzles.  Each is checked on the GPU with the LDS microbenchmarks
+// (fp8_ubench_lds_pattern, and fp8_ubench_lds_offsets over the 256 swizzles
+// that XOR row bits into the chunk index): a fragment read of 16 rows x 4
+// chunk positions must take the 4 LDS cycles of a conflict-free 128-bit read,
+// not 8.
 
-// Chunk c of tile row r sits at chunk c ^ g(r), g(r) = (r & 7) ^ ((r >> 3) & 1):
-// any 8 consecutive rows use 8 different chunk slots (one 128-byte bank
-// sweep) and any 16 consecutive rows cover all 16 sixteen-byte slots of two
-// rows (one 256-byte sweep), so a fragment read of 16 rows is conflict-free
-// whether the LDS serves 8 or 16 lanes of a 128-bit read per cycle.
+// Compressed rows (64 value bytes) keep their 16-byte chunk c at c ^ h(r),
+// h(r) = ((r >> 1) & 1) ^ (((r >> 3) & 1) << 1).  (The earlier
+// ((r >> 1) & 3) ^ ((r >> 3) & 1), and the unswizzled layout, cost 8 cycles.)
+__device__ __forceinline__ int swz_sp(int r, int c)
+{
+    return r * 64 + ((c ^ ((r >> 1) & 1) ^ (((r >> 3) & 1) << 1)) << 4);
+}
+
+// Dense rows (128 bytes) of the dense kernels: chunk c of row r sits at
+// c ^ g(r), g(r) = (r & 7) ^ ((r >> 3) & 1); the dense fragment reads chunk
+// positions (2g, 2g + 1) in two conflict-free instructions.
 __device__ __forceinline__ int swz(int r, int c) { return (r * 128) + ((c ^ (r & 7) ^ ((r >> 3) & 1)) << 4); }
+
+// Dense B rows of the 2:4 kernels: the 2:4 instruction reads chunk
+// positions (g, g + 4) instead of (2g, 2g + 1), which g(r) serves in 8
+// cycles; g2(r) = (r & 7) ^ (((r >> 3) & 1) << 1) serves them in 4.
+__device__ __forceinline__ int swz_b2(int r, int c)
+{
+    return (r * 128) + ((c ^ (r & 7) ^ (((r >> 3) & 1) << 1)) << 4);
+}
+// B-row swizzle of a kernel: SP (2:4 kernels) or dense.
+template <bool SP>
+__device__ __forceinline__ int swz_b(int r, int c) { return SP ? swz_b2(r, c) : swz(r, c); }
 
 // 16 bytes from global memory; `valid` (0..16) leading bytes are real, the
 // rest take `fill`.
@@ -472,10 +490,14 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     // source chunk is (l%8) ^ (l/8) ^ (q&1); round u of an odd number of
     // waves flips the last term, so a second offset serves those rounds.
     const int cd = (lane & 7) ^ (lane >> 3) ^ (wave & 1);
-    const int voff_b = (wave * 8 + (lane >> 3)) * (int)p.ldb + cd * 16;
+    // B rows of a 2:4 kernel use swz_b2: the block-parity term flips bit 1
+    const int fb = SP ? 2 : 1;
+    const int cb = (lane & 7) ^ (lane >> 3) ^ ((wave & 1) ? fb : 0);
+    const int voff_b = (wave * 8 + (lane >> 3)) * (int)p.ldb + cb * 16;
     // A: dense as B; compressed values (64 bytes): block q holds rows 16q ..
-    // 16q+15, lane l row 16q + l/4, slot l%4, chunk (l%4) ^ ((l>>3)&3) ^ (l>>5).
-    const int cs = (lane & 3) ^ ((lane >> 3) & 3) ^ (lane >> 5);
+    // 16q+15, lane l row 16q + l/4, slot l%4, chunk
+    // (l%4) ^ ((l>>3)&1) ^ ((l>>5) << 1) (swz_sp).
+    const int cs = (lane & 3) ^ ((lane >> 3) & 1) ^ ((lane >> 5) << 1);
     const int ca = SP ? cs : cd;
     const int voff_a = SP ? (wave * 16 + (lane >> 2)) * (int)p.lda + cs * 16 : (wave * 8 + (lane >> 3)) * (int)p.lda + cd * 16;
     // metadata (16 bytes per row): block q holds rows 64q .. 64q+63.
@@ -487,11 +509,11 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
         const uint32_t sb = lds0 + stage * S::STAGE;
         // whole chunks past the end of K read as zero: point them past the range
         const int va = SP ? (k0 / 2 + ca * 16 < Kv ? voff_a : rec_a) : (k0 + ca * 16 < kend ? voff_a : rec_a);
-        const int vb = k0 + cd * 16 < kend ? voff_b : rec_b;
+        const int vb = k0 + cb * 16 < kend ? voff_b : rec_b;
         // rounds whose block parity differs from the first one's (odd NW)
-        const int cdf = cd ^ 1;
+        const int cdf = cd ^ 1, cbf = cb ^ fb;
         const int vaf = SP ? va : (k0 + cdf * 16 < kend ? voff_a + (cdf - cd) * 16 : rec_a);
-        const int vbf = k0 + cdf * 16 < kend ? voff_b + (cdf - cd) * 16 : rec_b;
+        const int vbf = k0 + cbf * 16 < kend ? voff_b + (cbf - cb) * 16 : rec_b;
         constexpr int rows_a_blk = SP ? 16 : 8;   // rows per 1 KiB block
         static_for<0, RA>([&](auto uu) {
             constexpr int u = decltype(uu)::value;
@@ -537,8 +559,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     // (2048 bytes per 16 dense rows, 1024 per 16 compressed rows, 256 per
     // 16 metadata rows).
     const int rb0 = wn * WTN + lr, ra0 = wm * WTM + lr;
-    const int ob0 = S::A_BYTES + S::M_BYTES + swz(rb0, SP ? lg : 2 * lg);
-    const int ob1 = S::A_BYTES + S::M_BYTES + swz(rb0, SP ? lg + 4 : 2 * lg + 1);
+    const int ob0 = S::A_BYTES + S::M_BYTES + swz_b<SP>(rb0, SP ? lg : 2 * lg);
+    const int ob1 = S::A_BYTES + S::M_BYTES + swz_b<SP>(rb0, SP ? lg + 4 : 2 * lg + 1);
     const int oa0 = SP ? swz_sp(ra0, lg) : swz(ra0, 2 * lg);
     const int oa1 = SP ? S::A_BYTES + ra0 * 16 + lg * 4 : swz(ra0, 2 * lg + 1);
     auto compute = [&](int stage) {
@@ -1033,11 +1055,11 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
                 const int r = idx >> 2, c = idx & 3;
                 uint4 d0, d1;
                 expand24(kfast ? sel(rb[u], k0 / 2 + c * 16 < Kv, 0u) : rb[u], rmb[u], d0, d1);
-                *reinterpret_cast<uint4 *>(bb + swz(r, 2 * c)) = d0;
-                *reinterpret_cast<uint4 *>(bb + swz(r, 2 * c + 1)) = d1;
+                *reinterpret_cast<uint4 *>(bb + swz_b<SP>(r, 2 * c)) = d0;
+                *reinterpret_cast<uint4 *>(bb + swz_b<SP>(r, 2 * c + 1)) = d1;
             } else {
                 const int r = idx >> 3, c = idx & 7;
-                *reinterpret_cast<uint4 *>(bb + swz(r, c)) = kfast ? sel(rb[u], k0 + c * 16 < kend, 0u) : rb[u];
+                *reinterpret_cast<uint4 *>(bb + swz_b<SP>(r, c)) = kfast ? sel(rb[u], k0 + c * 16 < kend, 0u) : rb[u];
             }
         }
     };
@@ -1060,8 +1082,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             const int r = wn * WTN + j * 16 + lr;
-            uint4 lo = *reinterpret_cast<const uint4 *>(bb + swz(r, bc0));
-            uint4 hi = *reinterpret_cast<const uint4 *>(bb + swz(r, bc1));
+            uint4 lo = *reinterpret_cast<const uint4 *>(bb + swz_b<SP>(r, bc0));
+            uint4 hi = *reinterpret_cast<const uint4 *>(bb + swz_b<SP>(r, bc1));
             bf[j] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
         }
 #pragma unroll
@@ -1103,8 +1125,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 const int r = wn * WTN + j * 16 + lr;
-                uint4 lo = *reinterpret_cast<const uint4 *>(bb + swz(r, bc0));
-                uint4 hi = *reinterpret_cast<const uint4 *>(bb + swz(r, bc1));
+                uint4 lo = *reinterpret_cast<const uint4 *>(bb + swz_b<SP>(r, bc0));
+                uint4 hi = *reinterpret_cast<const uint4 *>(bb + swz_b<SP>(r, bc1));
                 gb[j] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
             }
         };

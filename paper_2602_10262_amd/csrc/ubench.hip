@@ -70,10 +70,12 @@ __global__ void __launch_bounds__(1024) mfma_rate(float *sink, int iters, int se
 // 16 x 128 K step, each lane l reading row (l % 16) of a 16-row block at
 // chunk positions g = l / 16: 1 dense operand (128-byte rows, chunk 2g, the
 // swizzle of the dense tiles), 2 compressed operand (64-byte rows, chunk g,
-// its swizzle), 3 dense operand read as the 2:4 B operand (chunk g + 4), 4
+// its swizzle), 3 the dense B operand of the 2:4 kernels (chunk g + 4, their
+// swizzle), 7 the same read on the dense tiles' swizzle (2-way conflicts), 4
 // metadata (16-byte rows, a 4-byte word g: ds_read_b32), 5 compressed
-// operand without swizzle (row r at r * 64).  Successive iterations move to
-// the next 16-row block (mod 256 rows).
+// operand without swizzle (row r at r * 64), 6 metadata of two 16-row blocks
+// 256 bytes apart in one instruction (ds_read2st64_b32).  Successive
+// iterations move to the next 16-row block (mod 256 rows).
 template <int P>
 __global__ void __launch_bounds__(1024) lds_rate(float *sink, int iters)
 {
@@ -90,18 +92,50 @@ __global__ void __launch_bounds__(1024) lds_rate(float *sink, int iters)
             const uint32_t v = *reinterpret_cast<const uint32_t *>(bytes + r * 16 + lg * 4);
             acc.x ^= v;
             acc.y += v;
+        } else if constexpr (P == 6) {
+            // the metadata words of two 16-row blocks at once (256 bytes apart:
+            // one ds_read2st64_b32, as the 2:4 GEMM reads them)
+            const uint32_t *m = reinterpret_cast<const uint32_t *>(bytes + (r & 127) * 16 + lg * 4);
+            const uint32_t v0 = m[0], v1 = m[64];
+            acc.x ^= v0;
+            acc.y += v1;
         } else {
             int off;
             if constexpr (P == 0) off = ((threadIdx.x + it * 64) & (slots - 1)) * 16;
             else if constexpr (P == 1) off = swz(r, 2 * lg);
             else if constexpr (P == 2) off = swz_sp(r, lg);
-            else if constexpr (P == 3) off = swz(r, lg + 4);
+            else if constexpr (P == 3) off = swz_b2(r, lg + 4);
+            else if constexpr (P == 7) off = swz(r, lg + 4);
             else off = r * 64 + lg * 16;
             const uint4 v = *reinterpret_cast<const uint4 *>(bytes + off);
             acc.x ^= v.x; acc.y += v.y; acc.z ^= v.z; acc.w += v.w;
         }
     }
-    if (acc.x == 0x12345678u && acc.y == 7u) sink[threadIdx.x] = 1.f;
+    // every word of every read feeds the condition, so no part of a read is dead
+    if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == 0x12345678u) sink[threadIdx.x] = 1.f;
+}
+
+// Arbitrary per-lane pattern: lane l of every wave reads 16 bytes at
+// off.v[l] + 2048 * (it % 16) of a 64 KiB buffer (offsets 16-byte aligned and
+// below 32 KiB), so any lane grouping or bank mapping can be probed.
+struct LaneOffsets {
+    int v[64];
+};
+
+__global__ void __launch_bounds__(1024) lds_rate_offsets(float *sink, int iters, LaneOffsets off)
+{
+    extern __shared__ uint4 lds_buf[];
+    const int slots = 4096;
+    for (int i = threadIdx.x; i < slots; i += blockDim.x) lds_buf[i] = make_uint4(i, i + 1, i + 2, i + 3);
+    __syncthreads();
+    const uint8_t *bytes = reinterpret_cast<const uint8_t *>(lds_buf);
+    const int base = off.v[threadIdx.x & 63];
+    uint4 acc = make_uint4(0, 0, 0, 0);
+    for (int it = 0; it < iters; ++it) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(bytes + base + 2048 * (it & 15));
+        acc.x ^= v.x; acc.y += v.y; acc.z ^= v.z; acc.w += v.w;
+    }
+    if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == 0x12345678u) sink[threadIdx.x] = 1.f;
 }
 
 template <int KIND, int U>
@@ -174,7 +208,7 @@ fp8_status fp8_ubench_mfma(int kind, int waves_per_cu, int chains, int iters, vo
 
 fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void *stream, double *ms)
 {
-    if (pattern < 0 || pattern > 5) return set_error(FP8_ERR_ARG, "pattern must be 0..5");
+    if (pattern < 0 || pattern > 7) return set_error(FP8_ERR_ARG, "pattern must be 0..7");
     if (waves_per_cu < 1 || waves_per_cu > 16 || iters < 1 || !ms) return set_error(FP8_ERR_ARG, "bad arguments");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     float *sink = nullptr;
@@ -191,7 +225,9 @@ fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void
     case 2: fn = (const void *)lds_rate<2>; break;
     case 3: fn = (const void *)lds_rate<3>; break;
     case 4: fn = (const void *)lds_rate<4>; break;
-    default: fn = (const void *)lds_rate<5>; break;
+    case 5: fn = (const void *)lds_rate<5>; break;
+    case 6: fn = (const void *)lds_rate<6>; break;
+    default: fn = (const void *)lds_rate<7>; break;
     }
     auto go = [&](int it) {
         switch (pattern) {
@@ -200,7 +236,9 @@ fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void
         case 2: lds_rate<2><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
         case 3: lds_rate<3><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
         case 4: lds_rate<4><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
-        default: lds_rate<5><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
+        case 5: lds_rate<5><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
+        case 6: lds_rate<6><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
+        default: lds_rate<7><<<cus, waves_per_cu * 64, lds, st>>>(sink, it); break;
         }
     };
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -211,6 +249,46 @@ fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void
         go(16);
         (void)hipEventRecord(e0, st);
         go(iters);
+        (void)hipEventRecord(e1, st);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0;
+    if (e == hipSuccess) (void)hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    if (e != hipSuccess) return hip_error(e, "LDS microbenchmark launch");
+    *ms = t;
+    return FP8_OK;
+}
+
+fp8_status fp8_ubench_lds_offsets(const int *lane_offsets, int waves_per_cu, int iters, void *stream, double *ms)
+{
+    if (!lane_offsets || !ms || waves_per_cu < 1 || waves_per_cu > 16 || iters < 1)
+        return set_error(FP8_ERR_ARG, "bad arguments");
+    LaneOffsets off;
+    for (int l = 0; l < 64; ++l) {
+        if (lane_offsets[l] < 0 || lane_offsets[l] >= 32768 || lane_offsets[l] % 16)
+            return set_error(FP8_ERR_ARG, "lane offsets must be 16-byte aligned and below 32768");
+        off.v[l] = lane_offsets[l];
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    float *sink = nullptr;
+    hipError_t e = hipMalloc(&sink, 1024 * sizeof(float));
+    if (e != hipSuccess) return hip_error(e, "sink");
+    const size_t lds = 64 * 1024;
+    int cus = 256, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    e = hipFuncSetAttribute((const void *)lds_rate_offsets, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    if (e == hipSuccess) {
+        lds_rate_offsets<<<cus, waves_per_cu * 64, lds, st>>>(sink, 16, off);
+        (void)hipEventRecord(e0, st);
+        lds_rate_offsets<<<cus, waves_per_cu * 64, lds, st>>>(sink, iters, off);
         (void)hipEventRecord(e1, st);
         e = hipGetLastError();
     }
