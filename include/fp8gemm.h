@@ -248,6 +248,7 @@ typedef struct {
     const float *a_scale; fp8_scale_kind a_kind;
     const float *b_scale; fp8_scale_kind b_kind;
     void *c; fp8_out c_type; int64_t ldc;
+    int tile_rows;            /* 0 = choose; 64, 128 or 256 (square tiles) */
 } fp8_hp_gemm_args;
 fp8_status fp8_hp_gemm(const fp8_hp_gemm_args *args, void *stream);
 

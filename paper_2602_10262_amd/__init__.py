@@ -52,7 +52,7 @@ class Sparse24BothGemmArgs(ctypes.Structure):
 class HpGemmArgs(ctypes.Structure):
     _fields_ = [("M", _I64), ("N", _I64), ("K", _I64), ("a", _P), ("lda", _I64), ("b", _P), ("ldb", _I64),
                 ("ab_type", _I), ("a_scale", _P), ("a_kind", _I), ("b_scale", _P), ("b_kind", _I),
-                ("c", _P), ("c_type", _I), ("ldc", _I64)]
+                ("c", _P), ("c_type", _I), ("ldc", _I64), ("tile_rows", _I)]
 
 
 class ChainStage(ctypes.Structure):
@@ -419,7 +419,7 @@ def fp8_sparse24_both_gemm_plan_resolve(args, plan=None):
 
 # ------------------------------------------------ higher-precision GEMM ----
 
-def fp8_hp_gemm(a, b_nk, a_scale=None, b_scale=None, out_dtype=None, c=None, stream=None):
+def fp8_hp_gemm(a, b_nk, a_scale=None, b_scale=None, out_dtype=None, c=None, stream=None, tile_rows=0):
     """C = diag(s_a) A B diag(s_b) for FP32, FP16 or BF16 tensors A (M x K) and
     B given as N x K rows; scales: None (1), one float or M / N floats."""
     import torch
@@ -438,7 +438,7 @@ def fp8_hp_gemm(a, b_nk, a_scale=None, b_scale=None, out_dtype=None, c=None, str
     args = HpGemmArgs(M, N, K, a.data_ptr(), a.stride(0), b_nk.data_ptr(), b_nk.stride(0), types[a.dtype],
                       a_scale.data_ptr(), FP8_SCALE_ROW if a_scale.numel() > 1 else FP8_SCALE_TENSOR,
                       b_scale.data_ptr(), FP8_SCALE_ROW if b_scale.numel() > 1 else FP8_SCALE_TENSOR,
-                      c.data_ptr(), _out_type(c.dtype), c.stride(0))
+                      c.data_ptr(), _out_type(c.dtype), c.stride(0), tile_rows)
     _call("fp8_hp_gemm", ctypes.byref(args), _stream(stream))
     return c
 

@@ -7,10 +7,10 @@
 // K (column-major K x N), C = (acc * s_a[i]) * s_b[j] stored as FP32, BF16 or
 // FP16 by the FP8 GEMM's epilogue.  Leading dimensions count elements.
 //
-// Pipeline: 256-byte LDS rows (64 FP32 or 128 16-bit elements of K per
-// step), two stages, loads of step k + 1 staged in registers during the
-// MFMAs of step k; 16-byte chunk x of row r sits at slot x ^ (r & 15), so
-// the sixteen rows of a fragment read hit sixteen different bank groups.
+// Pipeline: two LDS stages, loads of step k + 1 staged in registers during
+// the MFMAs of step k.  Tiles: 256 x 256 with 8 waves on 128-byte rows (32
+// FP32 or 64 16-bit elements of K per step), 128 x 128 and 64 x 64 with 4
+// waves on 256-byte rows (64 or 128 elements).
 // Lane l reads row l % 16 at chunk 4 s + l / 16 for sub-step s: 8 elements of
 // K for the 16-bit instruction (its K = 32 per sub-step), 4 for FP32, where
 // instruction t of the sub-step takes element t of every lane's chunk (any
@@ -27,23 +27,34 @@ namespace {
 
 constexpr int kHpF32 = 0, kHpF16 = 1, kHpBF16 = 2;
 
-template <int BM, int BN>
+// RB: bytes of K per LDS row and step (256: chunk x of row r at x ^ (r & 15);
+// 128: the 2:4 kernels' B swizzle, conflict-free for chunk positions (g, g+4)).
+template <int BM, int BN, int RB>
 struct HpSmem {
-    static constexpr int STAGE = (BM + BN) * 256;
+    static constexpr int STAGE = (BM + BN) * RB;
     static constexpr int TOTAL = 2 * STAGE;
 };
 
-template <int BM, int BN, int WM, int WN, int T>
+template <int RB>
+__device__ __forceinline__ int hp_slot(int r, int x)
+{
+    if constexpr (RB == 256) return r * 256 + ((x ^ (r & 15)) << 4);
+    else return swz_b2(r, x);
+}
+
+template <int BM, int BN, int WM, int WN, int T, int RB>
 __device__ __forceinline__ void gemm_tile_hp(const GemmParams &p, int tm, int tn, uint8_t *smem)
 {
     constexpr int ES = T == kHpF32 ? 4 : 2;
-    constexpr int KS = 256 / ES;
+    constexpr int KS = RB / ES;
+    constexpr int CH = RB / 16;            // 16-byte chunks per row and step
+    constexpr int SUB = RB / 64;           // sub-steps (four chunk positions each)
     constexpr int NT = WM * WN * 64;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
-    constexpr int A_U = BM * 16, B_U = BN * 16;
+    constexpr int A_U = BM * CH, B_U = BN * CH;
     constexpr int A_PER = (A_U + NT - 1) / NT, B_PER = (B_U + NT - 1) / NT;
-    using S = HpSmem<BM, BN>;
+    using S = HpSmem<BM, BN, RB>;
     static_assert(TM >= 1 && TN >= 1, "wave tile");
 
     const int tid = threadIdx.x;
@@ -61,7 +72,7 @@ __device__ __forceinline__ void gemm_tile_hp(const GemmParams &p, int tm, int tn
         for (int u = 0; u < A_PER; ++u) {
             const int idx = tid + u * NT;
             if (A_U % NT != 0 && idx >= A_U) break;
-            const int r = idx >> 4, c = idx & 15, row = m0 + r;
+            const int r = idx / CH, c = idx % CH, row = m0 + r;
             ra[u] = row < p.M ? load_codes16(p.a + (int64_t)row * p.lda * ES, kb + 16 * c, rowbytes)
                               : make_uint4(0, 0, 0, 0);
         }
@@ -69,13 +80,13 @@ __device__ __forceinline__ void gemm_tile_hp(const GemmParams &p, int tm, int tn
         for (int u = 0; u < B_PER; ++u) {
             const int idx = tid + u * NT;
             if (B_U % NT != 0 && idx >= B_U) break;
-            const int r = idx >> 4, c = idx & 15, row = n0 + r;
+            const int r = idx / CH, c = idx % CH, row = n0 + r;
             rb[u] = row < p.N ? load_codes16(p.b + (int64_t)row * p.ldb * ES, kb + 16 * c, rowbytes)
                               : make_uint4(0, 0, 0, 0);
         }
     };
     auto put = [&](uint8_t *base, int r, int x, const uint4 &v) {
-        *reinterpret_cast<uint4 *>(base + r * 256 + ((x ^ (r & 15)) << 4)) = v;
+        *reinterpret_cast<uint4 *>(base + hp_slot<RB>(r, x)) = v;
     };
     auto sstore = [&](int buf) {
         uint8_t *base = smem + buf * S::STAGE;
@@ -83,14 +94,14 @@ __device__ __forceinline__ void gemm_tile_hp(const GemmParams &p, int tm, int tn
         for (int u = 0; u < A_PER; ++u) {
             const int idx = tid + u * NT;
             if (A_U % NT != 0 && idx >= A_U) break;
-            put(base, idx >> 4, idx & 15, ra[u]);
+            put(base, idx / CH, idx % CH, ra[u]);
         }
-        uint8_t *bb = base + BM * 256;
+        uint8_t *bb = base + BM * RB;
 #pragma unroll
         for (int u = 0; u < B_PER; ++u) {
             const int idx = tid + u * NT;
             if (B_U % NT != 0 && idx >= B_U) break;
-            put(bb, idx >> 4, idx & 15, rb[u]);
+            put(bb, idx / CH, idx % CH, rb[u]);
         }
     };
 
@@ -101,13 +112,13 @@ __device__ __forceinline__ void gemm_tile_hp(const GemmParams &p, int tm, int tn
         for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
     auto chunk = [&](const uint8_t *base, int r, int x) {
-        return *reinterpret_cast<const uint4 *>(base + r * 256 + ((x ^ (r & 15)) << 4));
+        return *reinterpret_cast<const uint4 *>(base + hp_slot<RB>(r, x));
     };
     auto compute = [&](int buf) {
         const uint8_t *base = smem + buf * S::STAGE;
-        const uint8_t *bb = base + BM * 256;
+        const uint8_t *bb = base + BM * RB;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < SUB; ++s) {
             uint4 bf[TN];
 #pragma unroll
             for (int j = 0; j < TN; ++j) bf[j] = chunk(bb, wn * WTN + j * 16 + lr, 4 * s + lg);
@@ -156,23 +167,23 @@ __device__ __forceinline__ void gemm_tile_hp(const GemmParams &p, int tm, int tn
     write_tile<BM, BN, WM, WN, false, S::TOTAL>(p, acc, m0, n0, wave, lane, 0, smem);
 }
 
-template <int BM, int BN, int WM, int WN, int OCC, int T>
+template <int BM, int BN, int WM, int WN, int OCC, int T, int RB>
 __global__ void __launch_bounds__(WM *WN * 64, OCC) gemm_hp_kernel(GemmParams p)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t smem[HpSmem<BM, BN>::TOTAL];
+    __shared__ __attribute__((aligned(16))) uint8_t smem[HpSmem<BM, BN, RB>::TOTAL];
     int tm, tn;
     tile_coords<BM, BN>(p.M, p.N, tm, tn);
-    gemm_tile_hp<BM, BN, WM, WN, T>(p, tm, tn, smem);
+    gemm_tile_hp<BM, BN, WM, WN, T, RB>(p, tm, tn, smem);
 }
 
-template <int BM, int BN, int WM, int WN, int OCC>
+template <int BM, int BN, int WM, int WN, int OCC, int RB>
 hipError_t launch_hp(int t, const GemmParams &p, hipStream_t st)
 {
     const int nb = ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN);
     const dim3 grid((unsigned)nb), block(WM * WN * 64);
-    if (t == kHpF32) gemm_hp_kernel<BM, BN, WM, WN, OCC, kHpF32><<<grid, block, 0, st>>>(p);
-    else if (t == kHpF16) gemm_hp_kernel<BM, BN, WM, WN, OCC, kHpF16><<<grid, block, 0, st>>>(p);
-    else gemm_hp_kernel<BM, BN, WM, WN, OCC, kHpBF16><<<grid, block, 0, st>>>(p);
+    if (t == kHpF32) gemm_hp_kernel<BM, BN, WM, WN, OCC, kHpF32, RB><<<grid, block, 0, st>>>(p);
+    else if (t == kHpF16) gemm_hp_kernel<BM, BN, WM, WN, OCC, kHpF16, RB><<<grid, block, 0, st>>>(p);
+    else gemm_hp_kernel<BM, BN, WM, WN, OCC, kHpBF16, RB><<<grid, block, 0, st>>>(p);
     return hipGetLastError();
 }
 
@@ -180,10 +191,11 @@ bool aligned16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15u) ==
 
 }  // namespace
 
-// Tile choice: 128 x 128 once there are enough such tiles for the chip,
-// else 64 x 64.
+// Tile choice: 256 x 256 (8 waves, 128-byte rows) once there are enough
+// such tiles for the chip, then 128 x 128 (4 waves), else 64 x 64.
 int hp_tile_rows(int64_t M, int64_t N)
 {
+    if (((M + 255) / 256) * ((N + 255) / 256) >= 256) return 256;
     return ((M + 127) / 128) * ((N + 127) / 128) >= 256 ? 128 : 64;
 }
 
@@ -206,6 +218,8 @@ fp8_status fp8_hp_gemm(const fp8_hp_gemm_args *a, void *stream)
         (a->b_kind != FP8_SCALE_TENSOR && a->b_kind != FP8_SCALE_ROW))
         return set_error(FP8_ERR_ARG, "unknown scale kind");
     if (!a->a || !a->b || !a->c || !a->a_scale || !a->b_scale) return set_error(FP8_ERR_ARG, "null pointer");
+    if (a->tile_rows != 0 && a->tile_rows != 64 && a->tile_rows != 128 && a->tile_rows != 256)
+        return set_error(FP8_ERR_ARG, "tile_rows must be 0, 64, 128 or 256");
     if (a->lda < a->K || a->ldb < a->K || a->ldc < a->N) return set_error(FP8_ERR_ARG, "leading dimension too small");
     const int es = a->ab_type == FP8_HP_F32 ? 4 : 2;
     if ((int64_t)256 * a->lda * es >= ((int64_t)1 << 31) || (int64_t)256 * a->ldb * es >= ((int64_t)1 << 31))
@@ -226,8 +240,11 @@ fp8_status fp8_hp_gemm(const fp8_hp_gemm_args *a, void *stream)
     p.kchunk = p.K;
     const int t = a->ab_type == FP8_HP_F32 ? 0 : (a->ab_type == FP8_HP_F16 ? 1 : 2);
     const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const hipError_t e = hp_tile_rows(a->M, a->N) == 128 ? launch_hp<128, 128, 2, 2, 1>(t, p, st)
-                                                         : launch_hp<64, 64, 2, 2, 2>(t, p, st);
+    const int rows = a->tile_rows > 0 ? a->tile_rows : hp_tile_rows(a->M, a->N);
+    hipError_t e;
+    if (rows == 256) e = launch_hp<256, 256, 2, 4, 1, 128>(t, p, st);
+    else if (rows == 128) e = launch_hp<128, 128, 2, 2, 1, 256>(t, p, st);
+    else e = launch_hp<64, 64, 2, 2, 2, 256>(t, p, st);
     if (e != hipSuccess) return hip_error(e, "higher-precision gemm launch");
     return FP8_OK;
 }

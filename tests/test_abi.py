@@ -115,3 +115,39 @@ def test_noalloc_entry_point_without_gpu():
     assert L.fp8_noalloc_scratch_bytes() == 32 << 20
     args = lib.GemmArgs()
     assert L.fp8_gemm_noalloc(ctypes.byref(args), None, None) == 2  # FP8_ERR_SHAPE: M = 0
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    """Every ctypes mirror of a header struct has the C layout: size and the
+    offset of each field, from a C program compiled against the header."""
+    import ctypes
+    import subprocess
+    import paper_2602_10262_amd as lib
+    pairs = {
+        "fp8_gemm_args": lib.GemmArgs, "fp8_plan": lib.Plan, "fp8_sparse24_gemm_args": lib.Sparse24GemmArgs,
+        "fp8_sparse24_both_gemm_args": lib.Sparse24BothGemmArgs, "fp8_hp_gemm_args": lib.HpGemmArgs,
+        "fp8_chain_stage": lib.ChainStage, "fp8_chain_stats": lib.ChainStats,
+        "fp8_group_problem": lib.GroupProblem, "fp8_server_config": lib.ServerConfig,
+        "fp8_request": lib.Request, "fp8_server_stats": lib.ServerStats, "fp8_breakeven": lib.Breakeven,
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{os.path.join(ROOT, "include", "fp8gemm.h")}"',
+             "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c = {}
+    for line in got:
+        if line:
+            name, field, val = line.split()
+            c[(name, field)] = int(val)
+    for cname, py in pairs.items():
+        assert c[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert c[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -157,3 +157,39 @@ def test_chain_rejects_bad_stages(gpu):
         gpu.Chain([(gpu.FP8_STAGE_FP8, torch.zeros((64, 100), dtype=torch.uint8, device="cuda"), None)], 8, 100, 1)
     with pytest.raises(gpu.Fp8Error):
         gpu.Chain([(7, w, None)], 8, 100, 1)
+
+
+@pytest.mark.parametrize("tile_rows", [64, 128, 256])
+@pytest.mark.parametrize("ab", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("M,N,K", [(300, 200, 1000), (513, 257, 136), (40, 600, 3600)])
+def test_hp_gemm_every_tile(gpu, tile_rows, ab, M, N, K):
+    """Each tile of the FP32 / 16-bit GEMM (64 x 64 and 128 x 128 on 256-byte
+    LDS rows, 256 x 256 with 8 waves on 128-byte rows) on ragged shapes."""
+    import torch
+    dt = _dtypes()
+    xa = synth.normal_outliers(M + 3 * K, (M, K))
+    xb = synth.normal_outliers(N + 5 * K, (N, K))
+    a, b = _padded(xa, dt[ab]), _padded(xb, dt[ab])
+    c = gpu.fp8_hp_gemm(a, b, out_dtype=torch.float32, tile_rows=tile_rows)
+    torch.cuda.synchronize()
+    cref, sabs = orc.gemm_real(_values(a), _values(b))
+    res = orc.check(_values(c), cref, sabs, K, orc.OUT_F32)
+    log(f"hp tile {tile_rows} {ab} {M}x{N}x{K}: max_ratio={res['max_ratio']:.3e}")
+    assert res["ok"], res
+
+
+@pytest.mark.parametrize("ab", ["f32", "bf16"])
+def test_hp_gemm_4096_sampled_rows(gpu, ab):
+    """4096^3 on the default (256 x 256) tile: sampled rows against the oracle."""
+    import torch
+    dt = _dtypes()
+    M = N = K = 4096
+    g = torch.Generator(device="cuda").manual_seed(7)
+    a = torch.randn((M, K), generator=g, device="cuda").to(dt[ab])
+    b = torch.randn((N, K), generator=g, device="cuda").to(dt[ab])
+    c = gpu.fp8_hp_gemm(a, b, out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    rows = [0, 1, 255, 256, 2047, 4095]
+    cref, sabs = orc.gemm_real(_values(a[rows]), _values(b))
+    res = orc.check(_values(c[rows]), cref, sabs, K, orc.OUT_F32)
+    assert res["ok"], res
