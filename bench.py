@@ -751,7 +751,8 @@ def bench_ubench(lib, stream):
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     iters = 2000
-    out = {"cus": cus, "throughput": [], "latency": [], "lds": []}
+    out = {"cus": cus, "throughput": [], "latency": [], "lds": [],
+           "sclk_ghz_under_mfma_load": lib.fp8_ubench_clock(20000, stream)}
     for kind, (name, mnk) in lib.UBENCH_KINDS.items():
         for waves in (1, 2, 4, 8, 16):
             chains = 8 if kind in (0, 2) else 4
@@ -813,6 +814,8 @@ def main():
     ap.add_argument("--ubench-only", action="store_true", help="only the matrix-core and LDS microbenchmarks")
     ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision GEMMs and chains")
     ap.add_argument("--batching-only", action="store_true", help="only the per-request vs grouped batch study")
+    ap.add_argument("--served-only", action="store_true",
+                    help="only the served stream (with --served-sweep: all rates and budgets)")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the headline GEMM and its 2:4 form 3 times each and a 1 GiB device copy "
@@ -832,8 +835,15 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     M = N = K = args.size
-    if args.ace_only or args.ubench_only or args.mixed_only or args.batching_only:
-        if args.batching_only:
+    if args.ace_only or args.ubench_only or args.mixed_only or args.batching_only or args.served_only:
+        if args.served_only:
+            if args.served_sweep:
+                res = {"served": bench_served(lib, n_requests=args.requests,
+                                              rates=(0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 2.0),
+                                              budgets=(1 << 30, 2 << 30, 8 << 30))}
+            else:
+                res = {"served": bench_served(lib, n_requests=args.requests)}
+        elif args.batching_only:
             res = {"batching": bench_batching(lib, stream)}
         elif args.ace_only:
             res = {"ace": bench_ace(lib, stream)}

@@ -207,7 +207,7 @@ fp8_status fp8_sparse24_gemm(const fp8_sparse24_gemm_args *args, const fp8_plan 
  * operands: one operand feeds the 2:4 MFMA and the other is expanded to its
  * dense rows inside the kernel (never in memory), so it is read from HBM at
  * 0.625 bytes per element.  Plans: tiles 0, 3, 11, 12 (FP8 MFMA) and the
- * exact-sum tiles 25, 26 (chosen for K < 3584, as for the other GEMMs); any
+ * exact-sum tiles 25, 26, 27 (chosen for K < 3584, as for the other GEMMs); any
  * other tile is rejected with FP8_ERR_ARG.  Requirements: K % 8 == 0 and the
  * four compressed pointers 16-byte aligned.  The result equals fp8_gemm on
  * the two decompressed operands up to FP32 summation order. */
@@ -516,6 +516,14 @@ fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void
  * whose reads collide in a bank takes longer, so lane groupings and bank
  * mappings can be probed.  FP8_ERR_ARG for offsets outside that range. */
 fp8_status fp8_ubench_lds_offsets(const int *lane_offsets, int waves_per_cu, int iters, void *stream, double *ms);
+/* The engine clock under matrix-core load (the clock the measured MFMA rates
+ * run at, against the 2.4 GHz the peak figures assume): 8 waves per CU run the
+ * 16x16x128 FP8 MFMA loop for `iters` rounds of 8 instructions while one wave
+ * reads the shader clock counter and the constant-rate wall clock before and
+ * after; *ghz = clock ticks / wall seconds.  Blocking; allocates two small
+ * buffers for the call.  FP8_ERR_UNSUPPORTED if the device reports no wall
+ * clock rate. */
+fp8_status fp8_ubench_clock(int iters, void *stream, double *ghz);
 
 /* ------------------------------------------------------------------------ */
 /* Validator support: FP64 error norms on the device.                        */

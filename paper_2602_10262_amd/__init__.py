@@ -118,6 +118,7 @@ _SIGS = {
     "fp8_ubench_lds": [_I, _I, _P, _P],
     "fp8_ubench_lds_pattern": [_I, _I, _I, _P, _P],
     "fp8_ubench_lds_offsets": [_P, _I, _I, _P, _P],
+    "fp8_ubench_clock": [_I, _P, _P],
     "fp8_hp_gemm": [_P, _P],
     "fp8_chain_create": [_P, _I, _I64, _I64, _I, _I, _P],
     "fp8_chain_buffer": [_P, _I, _I, _P, _P],
@@ -613,6 +614,13 @@ def fp8_ubench_lds_pattern(pattern: int, waves_per_cu: int, iters: int, stream=N
     ms = ctypes.c_double(0)
     _call("fp8_ubench_lds_pattern", pattern, waves_per_cu, iters, _stream(stream), ctypes.byref(ms))
     return ms.value
+
+
+def fp8_ubench_clock(iters: int = 20000, stream=None) -> float:
+    """Engine clock (GHz) under 16x16x128 FP8 MFMA load."""
+    ghz = ctypes.c_double(0)
+    _call("fp8_ubench_clock", iters, _stream(stream), ctypes.byref(ghz))
+    return ghz.value
 
 
 def fp8_ubench_lds_offsets(lane_offsets, waves_per_cu: int, iters: int, stream=None) -> float:

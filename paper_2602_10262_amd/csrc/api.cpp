@@ -148,9 +148,10 @@ fp8_plan heuristic_plan(const GemmKey &k)
     fp8_plan p;
     const int64_t M = k.mk, N = k.nk;
     if (k.kk < kExactBelowK) {
-        // exact-sum tiles: 128 x 128 once there are enough such tiles to fill
-        // the chip, else 64 x 64 (split-K below adds workgroups)
-        p.tile = cdiv(M, 128) * cdiv(N, 128) >= 256 ? 25 : 26;
+        // exact-sum tiles: 128 x 128 with 8 waves (two per SIMD) once there
+        // are enough such tiles to fill the chip, else 64 x 64 (split-K
+        // below adds workgroups)
+        p.tile = cdiv(M, 128) * cdiv(N, 128) >= 256 ? 27 : 26;
         const TileDesc &t = tile_desc(p.tile);
         p.split_k = default_splits(cdiv(M, t.bm) * cdiv(N, t.bn), k.kk);
         return p;
@@ -165,8 +166,8 @@ fp8_plan heuristic_plan(const GemmKey &k)
     else if (M <= 64) p.tile = 7;
     else if (M <= 128 || N <= 128) p.tile = 0;
     // up to 1024 x 1024 outputs: 128 x 16 tiles give 8x the workgroups of
-    // 128 x 128 (measured 10.3 vs 16.2 us at 1024^3)
-    else if (!k.sparse && M * N <= (int64_t)1024 * 1024) p.tile = 8;
+    // 128 x 128 (measured 10.3 vs 16.2 us at 1024^3), dense and 2:4 alike
+    else if (M * N <= (int64_t)1024 * 1024) p.tile = 8;
     // 256 x 256 with LDS DMA: 128 x 64 wave tiles read 25% less LDS per
     // MFMA than 64 x 64 ones and no registers stage the loads; it wins once
     // there are enough tiles to fill the chip
@@ -429,7 +430,7 @@ static fp8_status prepare_both(const fp8_sparse24_both_gemm_args *s, Prepared &o
 static fp8_status resolve_both(const Prepared &pr, const fp8_plan *plan, fp8_plan &res)
 {
     const int64_t M = pr.p.M, N = pr.p.N, K = pr.p.K;
-    if (K < kExactBelowK) res.tile = cdiv(M, 128) * cdiv(N, 128) >= 256 ? 25 : 26;
+    if (K < kExactBelowK) res.tile = cdiv(M, 128) * cdiv(N, 128) >= 256 ? 27 : 26;
     else if (M >= 4096 && N >= 4096) res.tile = 12;
     else if (M <= 64 || N <= 64) res.tile = 3;
     else res.tile = 0;

@@ -13,7 +13,7 @@
 namespace fp8k {
 
 // Tiles with a both-sides kernel (indices into the tile table).
-#define FP8_BOTH_TILES(X) X(0) X(3) X(11) X(12) X(25) X(26)
+#define FP8_BOTH_TILES(X) X(0) X(3) X(11) X(12) X(25) X(26) X(27)
 
 template <int BM, int BN, int WM, int WN, int OCC, int PF, int FA, int FB, bool KFAST>
 __global__ void __launch_bounds__(WM *WN * 64, OCC) gemm_both_kernel(GemmParams p)

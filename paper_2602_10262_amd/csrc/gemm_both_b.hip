@@ -6,6 +6,7 @@ FP8_BOTH_INSTANTIATE(0)
 FP8_BOTH_INSTANTIATE(3)
 FP8_BOTH_INSTANTIATE(25)
 FP8_BOTH_INSTANTIATE(26)
+FP8_BOTH_INSTANTIATE(27)
 
 bool both_tile_supported(int tile)
 {

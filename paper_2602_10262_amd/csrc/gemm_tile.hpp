@@ -78,7 +78,8 @@ __device__ __forceinline__ void static_for(F &&f)
     X(23, 128, 256, 2, 4, 1, 7)    \
     X(24, 16, 32, 1, 1, 2, 16)     \
     X(25, 128, 128, 2, 2, 1, 40)   \
-    X(26, 64, 64, 2, 2, 2, 40)
+    X(26, 64, 64, 2, 2, 2, 40)     \
+    X(27, 128, 128, 2, 4, 1, 40)
 
 
 // Whether a tile of BM rows has a 2:4 kernel: its compressed rows fill whole

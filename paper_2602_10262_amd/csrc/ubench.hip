@@ -138,6 +138,39 @@ __global__ void __launch_bounds__(1024) lds_rate_offsets(float *sink, int iters,
     if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == 0x12345678u) sink[threadIdx.x] = 1.f;
 }
 
+// Engine clock under matrix-core load: every wave of every CU runs the
+// 16x16x128 FP8 MFMA throughput loop; wave 0 of block 0 reads the shader
+// clock counter (clock64) and the constant-rate wall clock (wall_clock64)
+// before and after its loop.
+__global__ void __launch_bounds__(1024) mfma_clock(float *sink, unsigned long long *stamps, int iters)
+{
+    const bool rec = blockIdx.x == 0 && threadIdx.x == 0;
+    unsigned long long c0 = 0, w0 = 0;
+    if (rec) {
+        c0 = clock64();
+        w0 = wall_clock64();
+    }
+    v8i a, b;
+    for (int i = 0; i < 8; ++i) {
+        a[i] = (int)threadIdx.x + i;
+        b[i] = 3 + i;
+    }
+    v4f acc[8];
+    for (int u = 0; u < 8; ++u) acc[u] = v4f{0, 0, 0, 0};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            acc[u] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[u], 0, 0, 0, 0, 0, 0);
+    }
+    float s = 0;
+    for (int u = 0; u < 8; ++u) s += acc[u][0] + acc[u][1] + acc[u][2] + acc[u][3];
+    if (s == 1234.5f) sink[threadIdx.x] = s;
+    if (rec) {
+        stamps[0] = clock64() - c0;
+        stamps[1] = wall_clock64() - w0;
+    }
+}
+
 template <int KIND, int U>
 hipError_t launch_mfma(int waves, int iters, float *sink, hipStream_t st)
 {
@@ -300,6 +333,38 @@ fp8_status fp8_ubench_lds_offsets(const int *lane_offsets, int waves_per_cu, int
     (void)hipFree(sink);
     if (e != hipSuccess) return hip_error(e, "LDS microbenchmark launch");
     *ms = t;
+    return FP8_OK;
+}
+
+fp8_status fp8_ubench_clock(int iters, void *stream, double *ghz)
+{
+    if (iters < 1 || !ghz) return set_error(FP8_ERR_ARG, "bad arguments");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int cus = 256, dev = 0, wall_khz = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess || wall_khz <= 0) return set_error(FP8_ERR_UNSUPPORTED, "no wall-clock rate");
+    float *sink = nullptr;
+    unsigned long long *stamps = nullptr;
+    e = hipMalloc(&sink, 1024 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&stamps, 2 * sizeof(unsigned long long));
+    const size_t lds = 96 * 1024;   // one workgroup per CU
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)mfma_clock, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    unsigned long long h[2] = {0, 0};
+    if (e == hipSuccess) {
+        mfma_clock<<<cus, 8 * 64, lds, st>>>(sink, stamps, 64);   // warm-up
+        mfma_clock<<<cus, 8 * 64, lds, st>>>(sink, stamps, iters);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(h, stamps, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(sink);
+    (void)hipFree(stamps);
+    if (e != hipSuccess) return hip_error(e, "clock microbenchmark");
+    if (h[1] == 0) return set_error(FP8_ERR_UNSUPPORTED, "wall clock did not advance");
+    *ghz = (double)h[0] / ((double)h[1] / (wall_khz * 1e3)) / 1e9;
     return FP8_OK;
 }
 

@@ -9,7 +9,7 @@ from tests.helpers import check_gemm, check_gemm_sampled, dev, log, operands
 
 pytestmark = pytest.mark.gpu
 
-BOTH_TILES = (0, 3, 11, 12, 25, 26)
+BOTH_TILES = (0, 3, 11, 12, 25, 26, 27)
 
 
 def _both(gpu, M, N, K, seed, fa, bf16, plan=None):
