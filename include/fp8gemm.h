@@ -510,12 +510,14 @@ fp8_status fp8_server_destroy(fp8_server *srv);                               /*
 fp8_status fp8_ubench_mfma(int kind, int waves_per_cu, int chains, int iters, void *stream, double *ms);
 fp8_status fp8_ubench_lds(int waves_per_cu, int iters, void *stream, double *ms);
 fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void *stream, double *ms);
-/* Any 128-bit read pattern: lane l of every wave reads 16 bytes at
- * lane_offsets[l] (64 host ints, 16-byte aligned, below 32768) plus a
- * per-iteration shift of a multiple of 2 KiB; times as above.  A lane pattern
- * whose reads collide in a bank takes longer, so lane groupings and bank
- * mappings can be probed.  FP8_ERR_ARG for offsets outside that range. */
-fp8_status fp8_ubench_lds_offsets(const int *lane_offsets, int waves_per_cu, int iters, void *stream, double *ms);
+/* Any 128-bit read (write = 0) or write (write = 1) pattern: lane l of every
+ * wave accesses 16 bytes at lane_offsets[l] (64 host ints, 16-byte aligned,
+ * below 32768) plus a per-iteration shift of a multiple of 2 KiB; times as
+ * above.  A lane pattern whose accesses collide in a bank takes longer, so
+ * lane groupings and bank mappings can be probed.  FP8_ERR_ARG for offsets
+ * outside that range. */
+fp8_status fp8_ubench_lds_offsets(const int *lane_offsets, int write, int waves_per_cu, int iters, void *stream,
+                                  double *ms);
 /* The engine clock under matrix-core load (the clock the measured MFMA rates
  * run at, against the 2.4 GHz the peak figures assume): 8 waves per CU run the
  * 16x16x128 FP8 MFMA loop for `iters` rounds of 8 instructions while one wave

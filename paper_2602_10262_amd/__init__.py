@@ -117,7 +117,7 @@ _SIGS = {
     "fp8_ubench_mfma": [_I, _I, _I, _I, _P, _P],
     "fp8_ubench_lds": [_I, _I, _P, _P],
     "fp8_ubench_lds_pattern": [_I, _I, _I, _P, _P],
-    "fp8_ubench_lds_offsets": [_P, _I, _I, _P, _P],
+    "fp8_ubench_lds_offsets": [_P, _I, _I, _I, _P, _P],
     "fp8_ubench_clock": [_I, _P, _P],
     "fp8_hp_gemm": [_P, _P],
     "fp8_chain_create": [_P, _I, _I64, _I64, _I, _I, _P],
@@ -623,10 +623,10 @@ def fp8_ubench_clock(iters: int = 20000, stream=None) -> float:
     return ghz.value
 
 
-def fp8_ubench_lds_offsets(lane_offsets, waves_per_cu: int, iters: int, stream=None) -> float:
+def fp8_ubench_lds_offsets(lane_offsets, waves_per_cu: int, iters: int, stream=None, write: bool = False) -> float:
     arr = (ctypes.c_int * 64)(*[int(o) for o in lane_offsets])
     ms = ctypes.c_double(0)
-    _call("fp8_ubench_lds_offsets", arr, waves_per_cu, iters, _stream(stream), ctypes.byref(ms))
+    _call("fp8_ubench_lds_offsets", arr, int(write), waves_per_cu, iters, _stream(stream), ctypes.byref(ms))
     return ms.value
 
 

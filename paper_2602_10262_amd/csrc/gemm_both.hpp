@@ -46,6 +46,9 @@ template <int T>
 hipError_t launch_both_tile(int fa, int fb, const GemmParams &p, hipStream_t st)
 {
     using C = TileCfg<T>;
+    if constexpr (C::PF == kExactPF) {
+        if (!k_is_fast(true, p.K)) return launch_both_one<C::BM, C::BN, C::WM, C::WN, C::OCC, C::PF, false>(fa, fb, p, st);
+    }
     return launch_both_one<C::BM, C::BN, C::WM, C::WN, C::OCC, C::PF, true>(fa, fb, p, st);
 }
 #define FP8_BOTH_EXTERN(i) extern template hipError_t launch_both_tile<i>(int, int, const GemmParams &, hipStream_t);

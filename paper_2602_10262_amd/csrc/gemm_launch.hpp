@@ -94,6 +94,10 @@ template <int T>
 hipError_t launch_tile(int fa, int fb, bool sp, const GemmParams &p, hipStream_t st)
 {
     using C = TileCfg<T>;
+    // an exact-sum tile loads byte-exact itself when K leaves partial chunks
+    if constexpr (C::PF == kExactPF) {
+        if (!k_is_fast(sp, p.K)) return launch_one<C::BM, C::BN, C::WM, C::WN, C::OCC, C::PF, false>(fa, fb, sp, p, st);
+    }
     return launch_one<C::BM, C::BN, C::WM, C::WN, C::OCC, C::PF>(fa, fb, sp, p, st);
 }
 #define FP8_EXTERN(i, bm, bn, wm, wn, occ, pf) \

@@ -22,6 +22,7 @@
 //   - epilogue: descales applied in FP32, C stored as FP32 or BF16 (RNE), or
 //     raw FP32 partial sums to the split-K workspace.
 #pragma once
+#include <type_traits>
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -624,10 +625,12 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
 // for every E4M3 and E5M2 code) and multiplies on the BF16 MFMA
 // (v_mfma_f32_16x16x32_bf16), whose products are exact and whose sums keep
 // 23 bits below the largest product of an instruction, so the bound holds
-// for every K.  Loads go through registers: the codes of step k + 1 are
-// loaded during step k and decoded into the other of two LDS stages after
-// it.  A 2:4 operand (values + index nibbles) is expanded to its dense row
-// while it is decoded, after which the step is a dense one.  LDS rows hold
+// for every K.  Loads go through registers: the codes of step k + 3 are
+// loaded at the start of step k (three register sets), and those of step
+// k + 1 are decoded into the other of two LDS stages between the MFMAs of
+// step k.  A 2:4
+// operand (values + index nibbles) is expanded to its dense row while it is
+// decoded, after which the step is a dense one.  LDS rows hold
 // 128 BF16 (256 bytes) with 16-byte chunk x of row r at x ^ (r & 15); lane l
 // reads row l % 16, codes 8 (l / 16) .. 8 (l / 16) + 7 of each 32 (one
 // chunk), for both operands; a lane's result is four consecutive i of one j.
@@ -679,7 +682,7 @@ __device__ __forceinline__ uint4 load_codes16(const uint8_t *row, int k, int len
     return load16_partial(row + k, max(0, min(16, len - k)), 0u);
 }
 
-template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool SPB = false>
+template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool SPB = false, bool KFAST = true>
 __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
 {
     constexpr int NT = WM * WN * 64;
@@ -702,9 +705,69 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
     const int nk = (kend - kbeg + kBK - 1) / kBK;
     const int Kv = p.K / 2, Km = p.K / 8;
 
-    uint4 ra[A_PER], rb[B_PER];
-    uint32_t rm[SP ? A_PER : 1], rmb[SPB ? B_PER : 1];
-    auto gload = [&](int kt) {
+    // NSET register sets: the loads of step k + NSET are issued at the start
+    // of step k, so global latency is hidden behind NSET steps of MFMAs
+    constexpr int NSET = 3;
+    uint4 ra[NSET][A_PER], rb[NSET][B_PER];
+    uint32_t rm[NSET][SP ? A_PER : 1], rmb[NSET][SPB ? B_PER : 1];
+    // Fast path (K a multiple of 16, or of 128 for a compressed operand):
+    // every chunk is one unconditional buffer load against a per-tile
+    // resource whose range ends at the last valid row, so rows past M or N
+    // read as zero, and a chunk past the end of the K range is pointed at the
+    // end of the range and reads as zero too.  With no branches around the
+    // loads the compiler counts them exactly and waits only for the set a
+    // store uses, not for every load in flight.
+    static_assert(NT % 8 == 0, "a thread keeps its chunk column across units");
+    const int rows_a = min(BM, p.M - m0), rows_b = min(BN, p.N - n0);
+    const int rec_a = rows_a * (int)p.lda, rec_b = rows_b * (int)p.ldb;
+    const int rec_m = SP ? rows_a * (int)p.ldm : 0, rec_mb = SPB ? rows_b * (int)p.ldmb : 0;
+    const __amdgpu_buffer_rsrc_t rs_a = uniform_rsrc(p.a + (int64_t)m0 * p.lda, rec_a);
+    const __amdgpu_buffer_rsrc_t rs_b = uniform_rsrc(p.b + (int64_t)n0 * p.ldb, rec_b);
+    const __amdgpu_buffer_rsrc_t rs_m = uniform_rsrc(SP ? p.meta + (int64_t)m0 * p.ldm : p.a, rec_m);
+    const __amdgpu_buffer_rsrc_t rs_mb = uniform_rsrc(SPB ? p.meta_b + (int64_t)n0 * p.ldmb : p.b, rec_mb);
+    // dense rows: unit u of a thread is row tid / 8 + u NT / 8, chunk tid % 8;
+    // compressed rows: row tid / 4 + u NT / 4, chunk tid % 4 (32 dense codes)
+    const int ca = SP ? (tid & 3) : (tid & 7), cb = SPB ? (tid & 3) : (tid & 7);
+    const int voff_a = SP ? (tid >> 2) * (int)p.lda + ca * 16 : (tid >> 3) * (int)p.lda + ca * 16;
+    const int voff_b = SPB ? (tid >> 2) * (int)p.ldb + cb * 16 : (tid >> 3) * (int)p.ldb + cb * 16;
+    const int voff_m = (tid >> 2) * (int)p.ldm + ca * 4, voff_mb = (tid >> 2) * (int)p.ldmb + cb * 4;
+    auto bload = [](const __amdgpu_buffer_rsrc_t &r, int voff, int soff) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    };
+    auto gload_fast = [&](int kt, auto ss) {
+        constexpr int st = decltype(ss)::value;
+        const int k0 = kbeg + kt * kBK;
+        // (the step's chunk column is the same for every unit of a thread)
+        const bool va = SP ? k0 / 2 + ca * 16 < kend / 2 : k0 + ca * 16 < kend;
+        const bool vb = SPB ? k0 / 2 + cb * 16 < kend / 2 : k0 + cb * 16 < kend;
+        const bool vm = k0 / 8 + ca * 4 < kend / 8, vmb = k0 / 8 + cb * 4 < kend / 8;
+#pragma unroll
+        for (int u = 0; u < A_PER; ++u) {
+            if (A_U % NT != 0 && tid + u * NT >= A_U) break;
+            constexpr int RPU = SP ? NT / 4 : NT / 8;   // rows per unit
+            ra[st][u] = bload(rs_a, va ? voff_a + u * RPU * (int)p.lda : rec_a, SP ? k0 / 2 : k0);
+            if constexpr (SP)
+                rm[st][u] = __builtin_amdgcn_raw_buffer_load_b32(rs_m, vm ? voff_m + u * RPU * (int)p.ldm : rec_m,
+                                                                 k0 / 8, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < B_PER; ++u) {
+            if (B_U % NT != 0 && tid + u * NT >= B_U) break;
+            constexpr int RPU = SPB ? NT / 4 : NT / 8;
+            rb[st][u] = bload(rs_b, vb ? voff_b + u * RPU * (int)p.ldb : rec_b, SPB ? k0 / 2 : k0);
+            if constexpr (SPB)
+                rmb[st][u] = __builtin_amdgcn_raw_buffer_load_b32(
+                    rs_mb, vmb ? voff_mb + u * RPU * (int)p.ldmb : rec_mb, k0 / 8, 0);
+        }
+    };
+    // Byte-exact path (any K): rows and chunks are clipped one by one.
+    auto gload = [&](int kt, auto ss) {
+        if constexpr (KFAST) {
+            gload_fast(kt, ss);
+            return;
+        }
+        constexpr int st = decltype(ss)::value;
         const int k0 = kbeg + kt * kBK;
 #pragma unroll
         for (int u = 0; u < A_PER; ++u) {
@@ -715,7 +778,7 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
                 // kept codes of dense positions [k0 + 32 c, k0 + 32 c + 32)
                 const int vk = k0 / 2 + 16 * c;
                 const int lim = min(Kv, kend / 2);
-                ra[u] = row < p.M ? load_codes16(p.a + (int64_t)row * p.lda, vk, lim) : make_uint4(0, 0, 0, 0);
+                ra[st][u] = row < p.M ? load_codes16(p.a + (int64_t)row * p.lda, vk, lim) : make_uint4(0, 0, 0, 0);
                 uint32_t m = 0;
                 if (row < p.M) {
                     const uint8_t *mr = p.meta + (int64_t)row * p.ldm + k0 / 8 + 4 * c;
@@ -723,10 +786,10 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
                     for (int b = 0; b < 4; ++b)
                         if (k0 / 8 + 4 * c + b < min(Km, kend / 8)) m |= (uint32_t)mr[b] << (8 * b);
                 }
-                rm[u] = m;
+                rm[st][u] = m;
             } else {
                 const int r = idx >> 3, c = idx & 7, row = m0 + r;
-                ra[u] = row < p.M ? load_codes16(p.a + (int64_t)row * p.lda, k0 + 16 * c, kend) : make_uint4(0, 0, 0, 0);
+                ra[st][u] = row < p.M ? load_codes16(p.a + (int64_t)row * p.lda, k0 + 16 * c, kend) : make_uint4(0, 0, 0, 0);
             }
         }
 #pragma unroll
@@ -737,7 +800,7 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
                 const int r = idx >> 2, c = idx & 3, row = n0 + r;
                 const int vk = k0 / 2 + 16 * c;
                 const int lim = min(Kv, kend / 2);
-                rb[u] = row < p.N ? load_codes16(p.b + (int64_t)row * p.ldb, vk, lim) : make_uint4(0, 0, 0, 0);
+                rb[st][u] = row < p.N ? load_codes16(p.b + (int64_t)row * p.ldb, vk, lim) : make_uint4(0, 0, 0, 0);
                 uint32_t m = 0;
                 if (row < p.N) {
                     const uint8_t *mr = p.meta_b + (int64_t)row * p.ldmb + k0 / 8 + 4 * c;
@@ -745,10 +808,10 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
                     for (int b = 0; b < 4; ++b)
                         if (k0 / 8 + 4 * c + b < min(Km, kend / 8)) m |= (uint32_t)mr[b] << (8 * b);
                 }
-                rmb[u] = m;
+                rmb[st][u] = m;
             } else {
                 const int r = idx >> 3, c = idx & 7, row = n0 + r;
-                rb[u] = row < p.N ? load_codes16(p.b + (int64_t)row * p.ldb, k0 + 16 * c, kend) : make_uint4(0, 0, 0, 0);
+                rb[st][u] = row < p.N ? load_codes16(p.b + (int64_t)row * p.ldb, k0 + 16 * c, kend) : make_uint4(0, 0, 0, 0);
             }
         }
     };
@@ -756,16 +819,20 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
     auto put = [&](uint8_t *base, int r, int x, const uint4 &v) {
         *reinterpret_cast<uint4 *>(base + r * 256 + ((x ^ (r & 15)) << 4)) = v;
     };
-    auto sstore = [&](int buf) {
+    // One register unit into LDS stage `buf`: units 0 .. A_PER - 1 are the A
+    // chunks of this thread, the next B_PER the B chunks.
+    constexpr int QT = A_PER + B_PER;
+    auto store_unit = [&](int buf, auto ss, auto qq) {
+        constexpr int st = decltype(ss)::value, q = decltype(qq)::value;
         uint8_t *base = smem + buf * S::STAGE;
-#pragma unroll
-        for (int u = 0; u < A_PER; ++u) {
+        if constexpr (q < A_PER) {
+            constexpr int u = q;
             const int idx = tid + u * NT;
-            if (A_U % NT != 0 && idx >= A_U) break;
+            if (A_U % NT != 0 && idx >= A_U) return;
             if constexpr (SP) {
                 const int r = idx >> 2, c = idx & 3;
                 uint4 d0, d1, b0, b1, b2, b3;
-                expand24(ra[u], rm[u], d0, d1);
+                expand24(ra[st][u], rm[st][u], d0, d1);
                 decode16<FA>(d0, b0, b1);
                 decode16<FA>(d1, b2, b3);
                 put(base, r, 4 * c, b0);
@@ -775,20 +842,19 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
             } else {
                 const int r = idx >> 3, c = idx & 7;
                 uint4 lo, hi;
-                decode16<FA>(ra[u], lo, hi);
+                decode16<FA>(ra[st][u], lo, hi);
                 put(base, r, 2 * c, lo);
                 put(base, r, 2 * c + 1, hi);
             }
-        }
-        uint8_t *bb = base + S::A_BYTES;
-#pragma unroll
-        for (int u = 0; u < B_PER; ++u) {
+        } else {
+            constexpr int u = q - A_PER;
+            uint8_t *bb = base + S::A_BYTES;
             const int idx = tid + u * NT;
-            if (B_U % NT != 0 && idx >= B_U) break;
+            if (B_U % NT != 0 && idx >= B_U) return;
             if constexpr (SPB) {
                 const int r = idx >> 2, c = idx & 3;
                 uint4 d0, d1, b0, b1, b2, b3;
-                expand24(rb[u], rmb[u], d0, d1);
+                expand24(rb[st][u], rmb[st][u], d0, d1);
                 decode16<FB>(d0, b0, b1);
                 decode16<FB>(d1, b2, b3);
                 put(bb, r, 4 * c, b0);
@@ -798,11 +864,14 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
             } else {
                 const int r = idx >> 3, c = idx & 7;
                 uint4 lo, hi;
-                decode16<FB>(rb[u], lo, hi);
+                decode16<FB>(rb[st][u], lo, hi);
                 put(bb, r, 2 * c, lo);
                 put(bb, r, 2 * c + 1, hi);
             }
         }
+    };
+    auto sstore = [&](int buf, auto ss) {
+        static_for<0, QT>([&](auto qq) { store_unit(buf, ss, qq); });
     };
 
     v4f acc[TM][TN];
@@ -818,11 +887,15 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
         __builtin_memcpy(&f, &v, 16);
         return f;
     };
-    auto compute = [&](int buf) {
+    // MFMAs of the step in LDS stage `buf`, four sub-steps of 32 codes; when
+    // `store` is set, the decode and LDS stores of the next step's register
+    // set (stage nbuf) follow each sub-step's MFMAs a quarter at a time, so
+    // they run while the matrix core works instead of after it.
+    auto compute = [&](int buf, int nbuf, bool store, auto ns) {
         const uint8_t *base = smem + buf * S::STAGE;
         const uint8_t *bb = base + S::A_BYTES;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {   // 32 codes of K per instruction
+        static_for<0, 4>([&](auto cc) {   // 32 codes of K per instruction
+            constexpr int c = decltype(cc)::value;
             v8bf bf[TN];
 #pragma unroll
             for (int j = 0; j < TN; ++j) bf[j] = frag(bb, wn * WTN + j * 16 + lr, 4 * c + lg);
@@ -832,18 +905,28 @@ __device__ __forceinline__ void gemm_tile_exact(const GemmParams &p, int tm, int
 #pragma unroll
                 for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[j], acc[i][j], 0, 0, 0);
             }
-        }
+            if (store) static_for<c * QT / 4, (c + 1) * QT / 4>([&](auto qq) { store_unit(nbuf, ns, qq); });
+        });
     };
 
     if (nk > 0) {
-        gload(0);
-        sstore(0);
+        static_for<0, NSET>([&](auto ss) {
+            if (decltype(ss)::value < nk) gload(decltype(ss)::value, ss);
+        });
+        sstore(0, std::integral_constant<int, 0>{});
         __syncthreads();
-        for (int kt = 0; kt < nk; ++kt) {
-            if (kt + 1 < nk) gload(kt + 1);
-            compute(kt & 1);
-            if (kt + 1 < nk) sstore((kt + 1) & 1);
-            __syncthreads();
+        // step k: loads of step k + NSET into the set step k used; MFMAs on
+        // LDS stage k % 2; step k + 1's set into the other stage; barrier
+        for (int kt0 = 0; kt0 < nk; kt0 += NSET) {
+            static_for<0, NSET>([&](auto ss) {
+                constexpr int st = decltype(ss)::value;
+                const int kt = kt0 + st;
+                if (kt < nk) {
+                    if (kt + NSET < nk) gload(kt + NSET, ss);
+                    compute(kt & 1, (kt + 1) & 1, kt + 1 < nk, std::integral_constant<int, (st + 1) % NSET>{});
+                    __syncthreads();
+                }
+            });
         }
     }
     write_tile<BM, BN, WM, WN, false, S::TOTAL>(p, acc, m0, n0, wave, lane, split, smem);
@@ -865,7 +948,7 @@ template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, bool KFAST = 
 __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
 {
     if constexpr (PF == kExactPF) {
-        gemm_tile_exact<BM, BN, WM, WN, FA, FB, SP, SPB>(p, tm, tn, split, smem);
+        gemm_tile_exact<BM, BN, WM, WN, FA, FB, SP, SPB, KFAST>(p, tm, tn, split, smem);
         return;
     } else if constexpr (PF >= 6) {
         static_assert(KFAST, "the DMA pipeline needs whole 16-byte chunks");

@@ -115,25 +115,36 @@ __global__ void __launch_bounds__(1024) lds_rate(float *sink, int iters)
     if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == 0x12345678u) sink[threadIdx.x] = 1.f;
 }
 
-// Arbitrary per-lane pattern: lane l of every wave reads 16 bytes at
-// off.v[l] + 2048 * (it % 16) of a 64 KiB buffer (offsets 16-byte aligned and
-// below 32 KiB), so any lane grouping or bank mapping can be probed.
+// Arbitrary per-lane pattern: lane l of every wave reads (or writes) 16 bytes
+// at off.v[l] + 2048 * (it % 16) of a 64 KiB buffer (offsets 16-byte aligned
+// and below 32 KiB), so any lane grouping or bank mapping can be probed.
 struct LaneOffsets {
     int v[64];
 };
 
-__global__ void __launch_bounds__(1024) lds_rate_offsets(float *sink, int iters, LaneOffsets off)
+__global__ void __launch_bounds__(1024) lds_rate_offsets(float *sink, int iters, LaneOffsets off, int write)
 {
     extern __shared__ uint4 lds_buf[];
     const int slots = 4096;
     for (int i = threadIdx.x; i < slots; i += blockDim.x) lds_buf[i] = make_uint4(i, i + 1, i + 2, i + 3);
     __syncthreads();
-    const uint8_t *bytes = reinterpret_cast<const uint8_t *>(lds_buf);
+    uint8_t *bytes = reinterpret_cast<uint8_t *>(lds_buf);
     const int base = off.v[threadIdx.x & 63];
-    uint4 acc = make_uint4(0, 0, 0, 0);
-    for (int it = 0; it < iters; ++it) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(bytes + base + 2048 * (it & 15));
-        acc.x ^= v.x; acc.y += v.y; acc.z ^= v.z; acc.w += v.w;
+    uint4 acc = make_uint4(threadIdx.x, 1, 2, 3);
+    if (write) {
+        // every wave writes its pattern; the values written depend on the
+        // iteration so no store is redundant
+        for (int it = 0; it < iters; ++it) {
+            acc.x += 1u;
+            *reinterpret_cast<uint4 *>(bytes + base + 2048 * (it & 15)) = acc;
+        }
+        __syncthreads();
+        acc = *reinterpret_cast<const uint4 *>(bytes + base);
+    } else {
+        for (int it = 0; it < iters; ++it) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(bytes + base + 2048 * (it & 15));
+            acc.x ^= v.x; acc.y += v.y; acc.z ^= v.z; acc.w += v.w;
+        }
     }
     if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == 0x12345678u) sink[threadIdx.x] = 1.f;
 }
@@ -296,7 +307,8 @@ fp8_status fp8_ubench_lds_pattern(int pattern, int waves_per_cu, int iters, void
     return FP8_OK;
 }
 
-fp8_status fp8_ubench_lds_offsets(const int *lane_offsets, int waves_per_cu, int iters, void *stream, double *ms)
+fp8_status fp8_ubench_lds_offsets(const int *lane_offsets, int write, int waves_per_cu, int iters, void *stream,
+                                  double *ms)
 {
     if (!lane_offsets || !ms || waves_per_cu < 1 || waves_per_cu > 16 || iters < 1)
         return set_error(FP8_ERR_ARG, "bad arguments");
@@ -319,9 +331,9 @@ fp8_status fp8_ubench_lds_offsets(const int *lane_offsets, int waves_per_cu, int
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     if (e == hipSuccess) {
-        lds_rate_offsets<<<cus, waves_per_cu * 64, lds, st>>>(sink, 16, off);
+        lds_rate_offsets<<<cus, waves_per_cu * 64, lds, st>>>(sink, 16, off, write);
         (void)hipEventRecord(e0, st);
-        lds_rate_offsets<<<cus, waves_per_cu * 64, lds, st>>>(sink, iters, off);
+        lds_rate_offsets<<<cus, waves_per_cu * 64, lds, st>>>(sink, iters, off, write);
         (void)hipEventRecord(e1, st);
         e = hipGetLastError();
     }

@@ -262,6 +262,22 @@ def test_exact_tiles_strict_bound_any_k(gpu, tile, M, N, K):
         check_gemm(c, qa, 1, qb, 0, da, db, False, f"exact tile {tile} split {split} {M}x{N}x{K}")
 
 
+@pytest.mark.parametrize("tile", EXACT_TILES)
+@pytest.mark.parametrize("M,N,K", [(150, 77, 2064), (97, 130, 1280), (260, 33, 136)])
+@pytest.mark.parametrize("sparse", [False, True])
+def test_exact_tiles_fast_and_byte_loaders(gpu, tile, M, N, K, sparse):
+    """Both loaders of the exact-sum tiles: buffer loads when K is a multiple
+    of 16 (dense) or 128 (compressed), the byte-exact loader otherwise; ragged
+    M and N, padded rows, split or not, against the strict bound."""
+    import torch
+    qa, da, qb, db = operands(M, N, K, 23, "normal", 0, 0, True)
+    for split in (1, 3):
+        log(f"exact loaders tile={tile} {M}x{N}x{K} sparse={sparse} split={split}")
+        c, qa_eff = _run_a_sparse_or_dense(gpu, qa, da, qb, db, sparse, (tile, split))
+        torch.cuda.synchronize()
+        check_gemm(c, qa_eff, 0, qb, 0, da, db, False, f"exact tile {tile} {M}x{N}x{K} sparse={sparse} split={split}")
+
+
 def _fp8_mfma_envelope(qa, da, qb, db, K):
     """The FP8 MFMA's measured error model: within each run of eight
     consecutive k (starting at multiples of 8) the products are aligned to the
