@@ -148,10 +148,17 @@ fp8_plan heuristic_plan(const GemmKey &k)
     fp8_plan p;
     const int64_t M = k.mk, N = k.nk;
     if (k.kk < kExactBelowK) {
-        // exact-sum tiles: 128 x 128 with 8 waves (two per SIMD) once there
-        // are enough such tiles to fill the chip, else 64 x 64 (split-K
-        // below adds workgroups)
-        p.tile = cdiv(M, 128) * cdiv(N, 128) >= 256 ? 27 : 26;
+        // exact-sum tiles.  Dense operands with whole 16-byte chunks: the
+        // DMA-ring tiles, 256 x 256 from about half a chip of such tiles
+        // (measured 3072^3: 79 us vs 89 for 128 x 128; 8192^2 x 2048: 223 vs
+        // 321), 128 x 128 from a full chip of those (2048^3: 25 us vs 30 on
+        // the register tile).  Otherwise the register tiles: 128 x 128 with 8
+        // waves once there are enough tiles to fill the chip, else 64 x 64
+        // (split-K below adds workgroups; 1024^3: 11 us vs 14).
+        const bool dma = !k.sparse && (k.kk % 16) == 0;
+        if (dma && cdiv(M, 256) * cdiv(N, 256) >= 128) p.tile = 30;
+        else if (cdiv(M, 128) * cdiv(N, 128) >= 256) p.tile = dma ? 28 : 27;
+        else p.tile = 26;
         const TileDesc &t = tile_desc(p.tile);
         p.split_k = default_splits(cdiv(M, t.bm) * cdiv(N, t.bn), k.kk);
         return p;

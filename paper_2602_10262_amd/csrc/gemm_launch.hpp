@@ -47,7 +47,7 @@ hipError_t launch_one(int fa, int fb, bool sp, const GemmParams &p, hipStream_t 
     dim3 grid((unsigned)nb, 1, (unsigned)p.splits), block(WM * WN * 64);
 #define FP8_GO(FA, FB, SP) gemm_kernel<BM, BN, WM, WN, OCC, PF, FA, FB, SP, KFAST><<<grid, block, 0, st>>>(p)
     constexpr bool DENSE = tile_dense_fits(BM, BN, PF);
-    constexpr bool SPARSE = tile_sparse_ok(BM) || PF == kExactPF;
+    constexpr bool SPARSE = (tile_sparse_ok(BM) || PF == kExactPF) && !pf_exact_dma(PF);
     // (plan resolution rejects a dense or 2:4 request for a tile without that kernel)
     if (sp) {
         if constexpr (SPARSE) {
@@ -94,9 +94,12 @@ template <int T>
 hipError_t launch_tile(int fa, int fb, bool sp, const GemmParams &p, hipStream_t st)
 {
     using C = TileCfg<T>;
-    // an exact-sum tile loads byte-exact itself when K leaves partial chunks
+    // an exact-sum tile loads byte-exact itself when K leaves partial chunks;
+    // the exact-sum DMA tiles hand such a K to the tile that does
     if constexpr (C::PF == kExactPF) {
         if (!k_is_fast(sp, p.K)) return launch_one<C::BM, C::BN, C::WM, C::WN, C::OCC, C::PF, false>(fa, fb, sp, p, st);
+    } else if constexpr (pf_exact_dma(C::PF)) {
+        if (!k_is_fast(sp, p.K)) return launch_tile<kExactAnyKTile>(fa, fb, sp, p, st);
     }
     return launch_one<C::BM, C::BN, C::WM, C::WN, C::OCC, C::PF>(fa, fb, sp, p, st);
 }

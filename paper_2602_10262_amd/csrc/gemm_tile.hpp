@@ -31,6 +31,12 @@ namespace fp8k {
 constexpr int kBK = 128;
 // Pipeline number of the exact-sum tiles (FP8 decoded to BF16, BF16 MFMA).
 constexpr int kExactPF = 40;
+// Pipelines kExactPF + 2 .. kExactPF + 4: exact sums on the LDS-DMA ring with
+// PF - kExactPF stages of FP8 codes, decoded after the fragment reads (dense
+// operands, K a multiple of 16; any other K runs on kExactAnyKTile).
+constexpr bool pf_exact_dma(int pf) { return pf >= kExactPF + 2 && pf <= kExactPF + 4; }
+constexpr bool pf_exact(int pf) { return pf == kExactPF || pf_exact_dma(pf); }
+constexpr int kExactAnyKTile = 27;
 // Buffer resource word 3 for raw (unswizzled, unformatted) dword access on gfx9.
 constexpr int kBufferFlags = 0x00020000;
 
@@ -80,7 +86,10 @@ __device__ __forceinline__ void static_for(F &&f)
     X(24, 16, 32, 1, 1, 2, 16)     \
     X(25, 128, 128, 2, 2, 1, 40)   \
     X(26, 64, 64, 2, 2, 2, 40)     \
-    X(27, 128, 128, 2, 4, 1, 40)
+    X(27, 128, 128, 2, 4, 1, 40)   \
+    X(28, 128, 128, 2, 4, 1, 44)   \
+    X(29, 256, 128, 4, 2, 1, 43)   \
+    X(30, 256, 256, 2, 4, 1, 42)
 
 
 // Whether a tile of BM rows has a 2:4 kernel: its compressed rows fill whole
@@ -90,8 +99,15 @@ constexpr bool tile_sparse_ok(int bm) { return bm % 64 == 0 || bm <= 32; }
 
 constexpr int kMaxLdsBytes = 160 * 1024;   // LDS of one CU (gfx950)
 
-// LDS of one tile: NSTAGE stages (2 for the register-prefetch loops, 3 for
-// the loop that also prefetches fragments, PF - 4 for the DMA loops).
+// Stages of pipeline pf: 2 for the register-prefetch loops, 3 for the loop
+// that also prefetches fragments, PF - 4 for the DMA loops, PF - kExactPF for
+// the exact-sum DMA loops.
+constexpr int pf_stages(int pf)
+{
+    return pf == 3 ? 3 : (pf == kExactPF ? 2 : (pf_exact_dma(pf) ? pf - kExactPF : (pf >= 6 ? pf - 4 : 2)));
+}
+
+// LDS of one tile: NSTAGE stages.
 template <int BM, int BN, bool SP, int PF = 2>
 struct TileSmem {
     // the exact-sum pipeline (PF == kExactPF) keeps both operands as BF16,
@@ -101,7 +117,7 @@ struct TileSmem {
     static constexpr int M_BYTES = (SP && !EXACT) ? BM * 16 : 0;
     static constexpr int B_BYTES = EXACT ? BN * 256 : BN * 128;
     static constexpr int STAGE = A_BYTES + M_BYTES + B_BYTES;
-    static constexpr int NSTAGE = PF == 3 ? 3 : (EXACT ? 2 : (PF >= 6 ? PF - 4 : 2));
+    static constexpr int NSTAGE = pf_stages(PF);
     static constexpr int TOTAL = NSTAGE * STAGE;
 };
 
@@ -109,8 +125,7 @@ struct TileSmem {
 // ring fits only with the compressed operand: 3 x 52 KiB).
 constexpr bool tile_dense_fits(int bm, int bn, int pf)
 {
-    return (pf == 3 ? 3 : (pf == kExactPF ? 2 : (pf >= 6 ? pf - 4 : 2))) *
-               ((pf == kExactPF ? 256 : 128) * (bm + bn)) <= kMaxLdsBytes;
+    return pf_stages(pf) * ((pf == kExactPF ? 256 : 128) * (bm + bn)) <= kMaxLdsBytes;
 }
 
 // LDS swizzles.  Each is checked on the GPU with the LDS microbenchmarks
@@ -437,6 +452,30 @@ __device__ __forceinline__ void wait_vm()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// FP8 -> BF16 with the hardware conversion, which is exact for every E4M3
+// and E5M2 code (both fit BF16's exponent range and mantissa).
+template <int FMT, bool HI>
+__device__ __forceinline__ uint32_t fp8x2_to_bf16x2(uint32_t w)
+{
+    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+    v2bf r;
+    if constexpr (FMT == kE4M3) r = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)w, 1.0f, HI);
+    else r = __builtin_amdgcn_cvt_scalef32_pk_bf16_bf8((int)w, 1.0f, HI);
+    uint32_t u;
+    __builtin_memcpy(&u, &r, 4);
+    return u;
+}
+
+// 16 FP8 codes (little-endian in q) -> 16 BF16 as two 16-byte chunks
+template <int FMT>
+__device__ __forceinline__ void decode16(const uint4 &q, uint4 &lo, uint4 &hi)
+{
+    lo = make_uint4(fp8x2_to_bf16x2<FMT, false>(q.x), fp8x2_to_bf16x2<FMT, true>(q.x),
+                    fp8x2_to_bf16x2<FMT, false>(q.y), fp8x2_to_bf16x2<FMT, true>(q.y));
+    hi = make_uint4(fp8x2_to_bf16x2<FMT, false>(q.z), fp8x2_to_bf16x2<FMT, true>(q.z),
+                    fp8x2_to_bf16x2<FMT, false>(q.w), fp8x2_to_bf16x2<FMT, true>(q.w));
+}
+
 // LDS-DMA pipeline (PF >= 6: NS = PF - 4 LDS stages).  Global tiles go
 // straight from memory into LDS without passing through registers, which
 // frees the staging registers for larger wave tiles (a 128 x 128 wave tile
@@ -565,7 +604,55 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     const int ob1 = S::A_BYTES + S::M_BYTES + swz_b<SP>(rb0, SP ? lg + 4 : 2 * lg + 1);
     const int oa0 = SP ? swz_sp(ra0, lg) : swz(ra0, 2 * lg);
     const int oa1 = SP ? S::A_BYTES + ra0 * 16 + lg * 4 : swz(ra0, 2 * lg + 1);
+    // Exact sums (pf_exact_dma): each lane reads 16-byte chunk 4 h + lg of
+    // its rows (h = 0, 1; conflict-free under swz, as every lane of a 16-row
+    // group reads the same chunk) and decodes it to 16 BF16; lane group lg
+    // feeds codes 64 h + 16 lg .. + 7 to one BF16 MFMA (32 k each) and the
+    // next eight to a second, in both operands, so the four MFMAs of a step
+    // cover its 128 k once each.
+    typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+    auto as_bf = [](const uint4 &v) {
+        v8bf f;
+        __builtin_memcpy(&f, &v, 16);
+        return f;
+    };
+    auto compute_exact = [&](int stage) {
+        const uint8_t *base = smem + stage * S::STAGE;
+        static_for<0, 2>([&](auto hh) {
+            constexpr int h = decltype(hh)::value;
+            const int ob = S::A_BYTES + swz(rb0, 4 * h + lg), oa = swz(ra0, 4 * h + lg);
+            v8bf blo[TN], bhi[TN];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                uint4 lo, hi;
+                decode16<FB>(*reinterpret_cast<const uint4 *>(base + ob + j * 2048), lo, hi);
+                blo[j] = as_bf(lo);
+                bhi[j] = as_bf(hi);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                uint4 lo, hi;
+                decode16<FA>(*reinterpret_cast<const uint4 *>(base + oa + i * 2048), lo, hi);
+                const v8bf alo = as_bf(lo), ahi = as_bf(hi);
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    if constexpr (SWAP) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(blo[j], alo, acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bhi[j], ahi, acc[i][j], 0, 0, 0);
+                    } else {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, blo[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi[j], acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+        });
+    };
     auto compute = [&](int stage) {
+        if constexpr (pf_exact_dma(PF)) {
+            static_assert(!SP, "exact sums on the DMA ring take dense operands");
+            compute_exact(stage);
+            return;
+        }
         const uint8_t *base = smem + stage * S::STAGE;
         v8i bf[TN];
 #pragma unroll
@@ -628,33 +715,14 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
 // for every K.  Loads go through registers: the codes of step k + 3 are
 // loaded at the start of step k (three register sets), and those of step
 // k + 1 are decoded into the other of two LDS stages between the MFMAs of
-// step k.  A 2:4
-// operand (values + index nibbles) is expanded to its dense row while it is
-// decoded, after which the step is a dense one.  LDS rows hold
-// 128 BF16 (256 bytes) with 16-byte chunk x of row r at x ^ (r & 15); lane l
-// reads row l % 16, codes 8 (l / 16) .. 8 (l / 16) + 7 of each 32 (one
-// chunk), for both operands; a lane's result is four consecutive i of one j.
-template <int FMT, bool HI>
-__device__ __forceinline__ uint32_t fp8x2_to_bf16x2(uint32_t w)
-{
-    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
-    v2bf r;
-    if constexpr (FMT == kE4M3) r = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)w, 1.0f, HI);
-    else r = __builtin_amdgcn_cvt_scalef32_pk_bf16_bf8((int)w, 1.0f, HI);
-    uint32_t u;
-    __builtin_memcpy(&u, &r, 4);
-    return u;
-}
-
-// 16 FP8 codes (little-endian in q) -> 16 BF16 as two 16-byte chunks
-template <int FMT>
-__device__ __forceinline__ void decode16(const uint4 &q, uint4 &lo, uint4 &hi)
-{
-    lo = make_uint4(fp8x2_to_bf16x2<FMT, false>(q.x), fp8x2_to_bf16x2<FMT, true>(q.x),
-                    fp8x2_to_bf16x2<FMT, false>(q.y), fp8x2_to_bf16x2<FMT, true>(q.y));
-    hi = make_uint4(fp8x2_to_bf16x2<FMT, false>(q.z), fp8x2_to_bf16x2<FMT, true>(q.z),
-                    fp8x2_to_bf16x2<FMT, false>(q.w), fp8x2_to_bf16x2<FMT, true>(q.w));
-}
+// step k.  A 2:4 operand (values + index nibbles) is expanded to its dense
+// row while it is decoded, after which the step is a dense one.  LDS rows
+// hold 128 BF16 (256 bytes) with 16-byte chunk x of row r at x ^ (r & 15);
+// lane l reads row l % 16, codes 8 (l / 16) .. 8 (l / 16) + 7 of each 32
+// (one chunk), for both operands; a lane's result is four consecutive i of
+// one j.  (Dense operands with K a multiple of 16 also have the exact-sum DMA
+// ring, pf_exact_dma, which keeps FP8 codes in LDS and decodes after the
+// fragment reads: half the LDS bytes per step.)
 
 // 16 kept codes of 32 dense positions (two per group of four, ascending) and
 // their eight index nibbles -> the 32 dense codes (zeros elsewhere)
@@ -949,6 +1017,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
 {
     if constexpr (PF == kExactPF) {
         gemm_tile_exact<BM, BN, WM, WN, FA, FB, SP, SPB, KFAST>(p, tm, tn, split, smem);
+        return;
+    } else if constexpr (pf_exact_dma(PF)) {
+        static_assert(KFAST && !SP && !SPB, "exact sums on the DMA ring: dense operands, whole 16-byte chunks");
+        gemm_tile_dma<BM, BN, WM, WN, FA, FB, false, PF - kExactPF, PF, SWAP>(p, tm, tn, split, smem);
         return;
     } else if constexpr (PF >= 6) {
         static_assert(KFAST, "the DMA pipeline needs whole 16-byte chunks");

@@ -42,8 +42,11 @@ def test_dense_ragged_shapes(gpu, M, N, K, fa, bf16):
     check_gemm(c, qa, fa, qb, 0, da, db, bf16, f"{M}x{N}x{K}")
 
 
-NUM_TILES = 28   # tile configurations the library exports (fp8_num_tiles)
-EXACT_TILES = (25, 26, 27)   # FP8 decoded to BF16, summed on the BF16 MFMA
+NUM_TILES = 31   # tile configurations the library exports (fp8_num_tiles)
+# FP8 decoded to BF16 and summed on the BF16 MFMA: 25-27 through registers
+# (any K, dense and 2:4), 28-30 on the LDS-DMA ring (dense, K % 16 == 0; any
+# other K runs on tile 27)
+EXACT_TILES = (25, 26, 27, 28, 29, 30)
 
 
 def test_tile_table_size(gpu):
@@ -271,11 +274,27 @@ def test_exact_tiles_fast_and_byte_loaders(gpu, tile, M, N, K, sparse):
     M and N, padded rows, split or not, against the strict bound."""
     import torch
     qa, da, qb, db = operands(M, N, K, 23, "normal", 0, 0, True)
+    if sparse and not gpu.fp8_tile_info(tile)["sparse"]:
+        # dense-only exact tile: a 2:4 plan is rejected before any launch
+        with pytest.raises(gpu.Fp8Error):
+            _run_a_sparse_or_dense(gpu, qa, da, qb, db, True, (tile, 1))
+        return
     for split in (1, 3):
         log(f"exact loaders tile={tile} {M}x{N}x{K} sparse={sparse} split={split}")
         c, qa_eff = _run_a_sparse_or_dense(gpu, qa, da, qb, db, sparse, (tile, split))
         torch.cuda.synchronize()
         check_gemm(c, qa_eff, 0, qb, 0, da, db, False, f"exact tile {tile} {M}x{N}x{K} sparse={sparse} split={split}")
+
+
+@pytest.mark.parametrize("M,N,K", [(2048, 2048, 2048), (4096, 1536, 1024), (1024, 1024, 1024)])
+def test_exact_default_plan_sampled(gpu, M, N, K):
+    """The library's own plan below K = 3584 at sweep sizes (many tiles of
+    the exact-sum kernels): sampled rows against the strict bound."""
+    import torch
+    qa, da, qb, db = operands(M, N, K, 29, "normal", 0, 0, True)
+    c = _run_dense(gpu, qa, qb, da, db, 0, 0, True)
+    torch.cuda.synchronize()
+    check_gemm_sampled(c, qa, 0, qb, 0, da, db, True, what=f"exact default plan {M}x{N}x{K}")
 
 
 def _fp8_mfma_envelope(qa, da, qb, db, K):
