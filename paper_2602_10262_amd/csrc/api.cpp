@@ -148,16 +148,23 @@ fp8_plan heuristic_plan(const GemmKey &k)
     fp8_plan p;
     const int64_t M = k.mk, N = k.nk;
     if (k.kk < kExactBelowK) {
-        // exact-sum tiles.  Dense operands with whole 16-byte chunks: the
-        // DMA-ring tiles, 256 x 256 from about half a chip of such tiles
-        // (measured 3072^3: 79 us vs 89 for 128 x 128; 8192^2 x 2048: 223 vs
-        // 321), 128 x 128 from a full chip of those (2048^3: 25 us vs 30 on
-        // the register tile).  Otherwise the register tiles: 128 x 128 with 8
-        // waves once there are enough tiles to fill the chip, else 64 x 64
-        // (split-K below adds workgroups; 1024^3: 11 us vs 14).
-        const bool dma = !k.sparse && (k.kk % 16) == 0;
-        if (dma && cdiv(M, 256) * cdiv(N, 256) >= 128) p.tile = 30;
-        else if (cdiv(M, 128) * cdiv(N, 128) >= 256) p.tile = dma ? 28 : 27;
+        // exact-sum tiles.  K in whole 16-byte chunks (128 codes with a 2:4
+        // operand): the 256 x 256 DMA-ring tile from about half a chip of
+        // such tiles, without split-K (measured dense 3072^3: 75 us vs 86 for
+        // 128 x 128 and 123 split four ways; 8192^2 x 2048: 226 vs 321; 2:4
+        // 314 vs 425 on the register tile).  Then 128 x 128 from a full chip
+        // of those: the DMA ring for dense operands (2048^3: 24 us vs 30),
+        // the register tile for a 2:4 one (31 us vs 37: the expansion after
+        // the fragment reads costs more than the ring saves).  Otherwise the
+        // 64 x 64 register tile (split-K below adds workgroups; 1024^3: 10
+        // us vs 14).
+        const bool dma = (k.kk % (k.sparse ? 128 : 16)) == 0;
+        if (dma && cdiv(M, 256) * cdiv(N, 256) >= 128) {
+            p.tile = 30;
+            p.split_k = 1;
+            return p;
+        }
+        if (cdiv(M, 128) * cdiv(N, 128) >= 256) p.tile = (dma && !k.sparse) ? 28 : 27;
         else p.tile = 26;
         const TileDesc &t = tile_desc(p.tile);
         p.split_k = default_splits(cdiv(M, t.bm) * cdiv(N, t.bn), k.kk);

@@ -32,8 +32,9 @@ constexpr int kBK = 128;
 // Pipeline number of the exact-sum tiles (FP8 decoded to BF16, BF16 MFMA).
 constexpr int kExactPF = 40;
 // Pipelines kExactPF + 2 .. kExactPF + 4: exact sums on the LDS-DMA ring with
-// PF - kExactPF stages of FP8 codes, decoded after the fragment reads (dense
-// operands, K a multiple of 16; any other K runs on kExactAnyKTile).
+// PF - kExactPF stages of FP8 codes (a 2:4 operand compressed), decoded (and
+// expanded) after the fragment reads; K a multiple of 16 (128 with a 2:4
+// operand), any other K runs on kExactAnyKTile.
 constexpr bool pf_exact_dma(int pf) { return pf >= kExactPF + 2 && pf <= kExactPF + 4; }
 constexpr bool pf_exact(int pf) { return pf == kExactPF || pf_exact_dma(pf); }
 constexpr int kExactAnyKTile = 27;
@@ -476,6 +477,21 @@ __device__ __forceinline__ void decode16(const uint4 &q, uint4 &lo, uint4 &hi)
                     fp8x2_to_bf16x2<FMT, false>(q.w), fp8x2_to_bf16x2<FMT, true>(q.w));
 }
 
+// 8 kept codes of 16 dense positions (two per group of four, ascending) and
+// their four index nibbles -> the 16 dense codes (zeros elsewhere)
+__device__ __forceinline__ uint4 expand24_half(uint2 v, uint32_t nibs)
+{
+    uint32_t d[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const uint32_t nib = (nibs >> (4 * g)) & 15u;
+        const uint32_t kw = g < 2 ? v.x : v.y, sh = 16 * (g & 1);
+        const uint32_t c0 = (kw >> sh) & 0xFFu, c1 = (kw >> (sh + 8)) & 0xFFu;
+        d[g] = (c0 << (8 * (nib & 3u))) | (c1 << (8 * (nib >> 2)));
+    }
+    return make_uint4(d[0], d[1], d[2], d[3]);
+}
+
 // LDS-DMA pipeline (PF >= 6: NS = PF - 4 LDS stages).  Global tiles go
 // straight from memory into LDS without passing through registers, which
 // frees the staging registers for larger wave tiles (a 128 x 128 wave tile
@@ -647,10 +663,45 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
             }
         });
     };
+    // The same with a compressed A: dense chunk x = 4 h + lg of a row is
+    // kept codes 8 x .. 8 x + 7 (half x % 2 of compressed chunk x / 2) and
+    // index nibbles 4 x .. 4 x + 3 (16 bits at byte 2 x of the row's
+    // metadata), expanded to 16 dense codes before the decode.
+    auto compute_exact_sp = [&](int stage) {
+        const uint8_t *base = smem + stage * S::STAGE;
+        static_for<0, 2>([&](auto hh) {
+            constexpr int h = decltype(hh)::value;
+            const int x = 4 * h + lg;
+            const int ob = S::A_BYTES + S::M_BYTES + swz_b2(rb0, x);
+            const int oa = swz_sp(ra0, x >> 1) + 8 * (x & 1), om = S::A_BYTES + ra0 * 16 + 2 * x;
+            v8bf blo[TN], bhi[TN];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                uint4 lo, hi;
+                decode16<FB>(*reinterpret_cast<const uint4 *>(base + ob + j * 2048), lo, hi);
+                blo[j] = as_bf(lo);
+                bhi[j] = as_bf(hi);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const uint2 kept = *reinterpret_cast<const uint2 *>(base + oa + i * 1024);
+                const uint32_t nibs = *reinterpret_cast<const uint16_t *>(base + om + i * 256);
+                uint4 lo, hi;
+                decode16<FA>(expand24_half(kept, nibs), lo, hi);
+                const v8bf alo = as_bf(lo), ahi = as_bf(hi);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, blo[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi[j], acc[i][j], 0, 0, 0);
+            }
+        });
+    };
     auto compute = [&](int stage) {
         if constexpr (pf_exact_dma(PF)) {
-            static_assert(!SP, "exact sums on the DMA ring take dense operands");
-            compute_exact(stage);
+            if constexpr (SP) compute_exact_sp(stage);
+            else compute_exact(stage);
             return;
         }
         const uint8_t *base = smem + stage * S::STAGE;
@@ -1019,8 +1070,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
         gemm_tile_exact<BM, BN, WM, WN, FA, FB, SP, SPB, KFAST>(p, tm, tn, split, smem);
         return;
     } else if constexpr (pf_exact_dma(PF)) {
-        static_assert(KFAST && !SP && !SPB, "exact sums on the DMA ring: dense operands, whole 16-byte chunks");
-        gemm_tile_dma<BM, BN, WM, WN, FA, FB, false, PF - kExactPF, PF, SWAP>(p, tm, tn, split, smem);
+        static_assert(KFAST && !SPB, "exact sums on the DMA ring: whole 16-byte chunks, dense j operand");
+        gemm_tile_dma<BM, BN, WM, WN, FA, FB, SP, PF - kExactPF, PF, SWAP>(p, tm, tn, split, smem);
         return;
     } else if constexpr (PF >= 6) {
         static_assert(KFAST, "the DMA pipeline needs whole 16-byte chunks");

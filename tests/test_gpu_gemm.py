@@ -44,8 +44,8 @@ def test_dense_ragged_shapes(gpu, M, N, K, fa, bf16):
 
 NUM_TILES = 31   # tile configurations the library exports (fp8_num_tiles)
 # FP8 decoded to BF16 and summed on the BF16 MFMA: 25-27 through registers
-# (any K, dense and 2:4), 28-30 on the LDS-DMA ring (dense, K % 16 == 0; any
-# other K runs on tile 27)
+# (any K), 28-30 on the LDS-DMA ring (K % 16 == 0, or % 128 with a 2:4
+# operand; any other K runs on tile 27); dense and 2:4 alike
 EXACT_TILES = (25, 26, 27, 28, 29, 30)
 
 
@@ -287,14 +287,38 @@ def test_exact_tiles_fast_and_byte_loaders(gpu, tile, M, N, K, sparse):
 
 
 @pytest.mark.parametrize("M,N,K", [(2048, 2048, 2048), (4096, 1536, 1024), (1024, 1024, 1024)])
-def test_exact_default_plan_sampled(gpu, M, N, K):
+@pytest.mark.parametrize("sparse", [False, True])
+def test_exact_default_plan_sampled(gpu, M, N, K, sparse):
     """The library's own plan below K = 3584 at sweep sizes (many tiles of
-    the exact-sum kernels): sampled rows against the strict bound."""
+    the exact-sum kernels), dense and 2:4 on A: sampled outputs against the
+    strict bound."""
     import torch
     qa, da, qb, db = operands(M, N, K, 29, "normal", 0, 0, True)
-    c = _run_dense(gpu, qa, qb, da, db, 0, 0, True)
+    log(f"exact default plan {M}x{N}x{K} sparse={sparse}")
+    if sparse:
+        va, ma, _, pa = orc.prune24(qa, 0)
+        c = gpu.fp8_sparse24_gemm(dev(va), dev(ma), codes_with_pad(N, K, qb), gpu.FP8_SPARSE_A, dev(da), dev(db),
+                                  out_dtype=torch.bfloat16)
+        qa = pa
+    else:
+        c = _run_dense(gpu, qa, qb, da, db, 0, 0, True)
     torch.cuda.synchronize()
-    check_gemm_sampled(c, qa, 0, qb, 0, da, db, True, what=f"exact default plan {M}x{N}x{K}")
+    check_gemm_sampled(c, qa, 0, qb, 0, da, db, True, what=f"exact default plan {M}x{N}x{K} sparse={sparse}")
+
+
+@pytest.mark.parametrize("tile", [28, 29, 30])
+def test_exact_dma_tiles_weight_side(gpu, tile):
+    """2:4 weight (B side) on the exact-sum DMA tiles, split or not."""
+    import torch
+    M, N, K = 130, 300, 1280
+    qa, da, qb, db = _sparse_case(M, N, K, 31)
+    vw, mw, _, pw = orc.prune24(qb, 0)
+    for split in (1, 3):
+        log(f"exact dma weight side tile={tile} split={split}")
+        c = gpu.fp8_sparse24_gemm(dev(vw), dev(mw), codes_with_pad(M, K, qa), gpu.FP8_SPARSE_B, dev(da), dev(db),
+                                  plan=(tile, split))
+        torch.cuda.synchronize()
+        check_gemm(c, qa, 0, pw, 0, da, db, False, f"exact dma weight side tile {tile} split {split}")
 
 
 def _fp8_mfma_envelope(qa, da, qb, db, K):
