@@ -972,6 +972,7 @@ def main():
         lib.fp8_tune_cache_save(os.path.join(ROOT, "gpurun_out", "tune_cache.jsonl")) if os.path.isdir(
             os.path.join(ROOT, "gpurun_out")) else None
 
+    sclk = extra["ubench"]["sclk_ghz_under_mfma_load"]
     out = {
         "metric": "FP8 TFLOP/s (% of peak) dense vs 2:4 sparse; grouped-serving p50/p99 latency",
         "value": value,
@@ -989,7 +990,12 @@ def main():
                                "descales, FP32 accumulate, BF16 out", "M": M, "N": N, "K": K,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP8_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP8_TFLOPS, "traffic": measured_traffic() if M == 8192 else None},
+                     "frac": achieved / PEAK_FP8_TFLOPS, "traffic": measured_traffic() if M == 8192 else None,
+                     # the peak assumes 2.4 GHz; the engine clock this GPU showed under an MFMA load
+                     # (s_memtime against the constant-rate wall clock), and the fraction of the
+                     # peak scaled to that clock
+                     "sclk_ghz_mfma_load": sclk,
+                     "frac_at_that_sclk": achieved / (PEAK_FP8_TFLOPS * sclk / 2.4) if sclk else None},
         "extra": extra,
     }
     if not args.no_cpu:
