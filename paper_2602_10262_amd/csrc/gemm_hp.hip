@@ -7,10 +7,12 @@
 // K (column-major K x N), C = (acc * s_a[i]) * s_b[j] stored as FP32, BF16 or
 // FP16 by the FP8 GEMM's epilogue.  Leading dimensions count elements.
 //
-// Pipeline: two LDS stages, loads of step k + 1 staged in registers during
-// the MFMAs of step k.  Tiles: 256 x 256 with 8 waves on 128-byte rows (32
-// FP32 or 64 16-bit elements of K per step), 128 x 128 and 64 x 64 with 4
-// waves on 256-byte rows (64 or 128 elements).
+// Pipelines: 256 x 256 with 8 waves on the FP8 tiles' two-stage LDS-DMA
+// ring (128-byte rows: 32 FP32 or 64 16-bit elements of K per step) when K
+// fills whole 16-byte chunks; otherwise two LDS stages with the loads of step
+// k + 1 staged in registers during the MFMAs of step k: 256 x 256 with 8
+// waves on 128-byte rows, 128 x 128 and 64 x 64 with 4 waves on 256-byte
+// rows (64 or 128 elements).
 // Lane l reads row l % 16 at chunk 4 s + l / 16 for sub-step s: 8 elements of
 // K for the 16-bit instruction (its K = 32 per sub-step), 4 for FP32, where
 // instruction t of the sub-step takes element t of every lane's chunk (any
@@ -24,8 +26,6 @@
 namespace fp8k {
 
 namespace {
-
-constexpr int kHpF32 = 0, kHpF16 = 1, kHpBF16 = 2;
 
 // RB: bytes of K per LDS row and step (256: chunk x of row r at x ^ (r & 15);
 // 128: the 2:4 kernels' B swizzle, conflict-free for chunk positions (g, g+4)).
@@ -176,6 +176,32 @@ __global__ void __launch_bounds__(WM *WN * 64, OCC) gemm_hp_kernel(GemmParams p)
     gemm_tile_hp<BM, BN, WM, WN, T, RB>(p, tm, tn, smem);
 }
 
+// The 256 x 256 tile on the FP8 tiles' LDS-DMA ring (two stages of 128-byte
+// rows, no staging registers); p counts K and the leading dimensions in bytes.
+template <int T>
+__global__ void __launch_bounds__(512, 1) gemm_hp_dma_kernel(GemmParams p)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t smem[TileSmem<256, 256, false, 6>::TOTAL];
+    int tm, tn;
+    tile_coords<256, 256>(p.M, p.N, tm, tn);
+    gemm_tile_dma<256, 256, 2, 4, 0, 0, false, 2, 6, true, T>(p, tm, tn, 0, smem);
+}
+
+hipError_t launch_hp_dma(int t, const GemmParams &p, int es, hipStream_t st)
+{
+    GemmParams q = p;
+    q.K = p.K * es;
+    q.lda = p.lda * es;
+    q.ldb = p.ldb * es;
+    q.kchunk = (q.K + kBK - 1) / kBK * kBK;
+    const int nb = ((p.M + 255) / 256) * ((p.N + 255) / 256);
+    const dim3 grid((unsigned)nb), block(512);
+    if (t == kHpF32) gemm_hp_dma_kernel<kHpF32><<<grid, block, 0, st>>>(q);
+    else if (t == kHpF16) gemm_hp_dma_kernel<kHpF16><<<grid, block, 0, st>>>(q);
+    else gemm_hp_dma_kernel<kHpBF16><<<grid, block, 0, st>>>(q);
+    return hipGetLastError();
+}
+
 template <int BM, int BN, int WM, int WN, int OCC, int RB>
 hipError_t launch_hp(int t, const GemmParams &p, hipStream_t st)
 {
@@ -242,7 +268,10 @@ fp8_status fp8_hp_gemm(const fp8_hp_gemm_args *a, void *stream)
     const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int rows = a->tile_rows > 0 ? a->tile_rows : hp_tile_rows(a->M, a->N);
     hipError_t e;
-    if (rows == 256) e = launch_hp<256, 256, 2, 4, 1, 128>(t, p, st);
+    // the DMA ring needs K in whole 16-byte chunks; other K take the
+    // register-staged 256 x 256 tile
+    if (rows == 256 && (p.K * es) % 16 == 0) e = launch_hp_dma(t, p, es, st);
+    else if (rows == 256) e = launch_hp<256, 256, 2, 4, 1, 128>(t, p, st);
     else if (rows == 128) e = launch_hp<128, 128, 2, 2, 1, 256>(t, p, st);
     else e = launch_hp<64, 64, 2, 2, 2, 256>(t, p, st);
     if (e != hipSuccess) return hip_error(e, "higher-precision gemm launch");

@@ -38,6 +38,9 @@ constexpr int kExactPF = 40;
 constexpr bool pf_exact_dma(int pf) { return pf >= kExactPF + 2 && pf <= kExactPF + 4; }
 constexpr bool pf_exact(int pf) { return pf == kExactPF || pf_exact_dma(pf); }
 constexpr int kExactAnyKTile = 27;
+// Operand types of the higher-precision GEMMs (the DMA ring's HP parameter;
+// -1 there means FP8 codes).
+constexpr int kHpF32 = 0, kHpF16 = 1, kHpBF16 = 2;
 // Buffer resource word 3 for raw (unswizzled, unformatted) dword access on gfx9.
 constexpr int kBufferFlags = 0x00020000;
 
@@ -506,7 +509,13 @@ __device__ __forceinline__ uint4 expand24_half(uint2 v, uint32_t nibs)
 // is (past the last step into a buffer nobody reads), so the wait count is a
 // constant; everything is drained before the workgroup ends.  Requires K to
 // be a multiple of 16 (dense) or 128 (compressed operand).
-template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, int NS, int PF, bool SWAP>
+// HP >= 0: the operands are FP32, FP16 or BF16 values instead of FP8 codes
+// (kHpF32 / kHpF16 / kHpBF16); p.K, p.kchunk, p.lda and p.ldb then count
+// bytes, so a step covers 128 bytes of K (32 or 64 elements), and each lane
+// reads chunk 4 h + g of its rows (h = 0, 1): 8 elements for one 16-bit MFMA,
+// 4 for four FP32 ones (instruction t takes element t), the same k mapping in
+// A and B.
+template <int BM, int BN, int WM, int WN, int FA, int FB, bool SP, int NS, int PF, bool SWAP, int HP = -1>
 __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int tn, int split, uint8_t *smem)
 {
     constexpr int NW = WM * WN;
@@ -698,7 +707,46 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
             }
         });
     };
+    auto compute_hp = [&](int stage) {
+        static_assert(HP < 0 || (!SP && !pf_exact_dma(PF)), "higher-precision operands: dense FP8-layout ring");
+        const uint8_t *base = smem + stage * S::STAGE;
+        static_for<0, 2>([&](auto hh) {
+            constexpr int h = decltype(hh)::value;
+            const int ob = S::A_BYTES + swz(rb0, 4 * h + lg), oa = swz(ra0, 4 * h + lg);
+            uint4 bq[TN];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bq[j] = *reinterpret_cast<const uint4 *>(base + ob + j * 2048);
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const uint4 aq = *reinterpret_cast<const uint4 *>(base + oa + i * 2048);
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    // SWAP: B rows in the instruction's A slot (row-major output lanes)
+                    const uint4 &x = SWAP ? bq[j] : aq, &y = SWAP ? aq : bq[j];
+                    if constexpr (HP == kHpF32) {
+                        const uint32_t x4[4] = {x.x, x.y, x.z, x.w}, y4[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x4[t]),
+                                                                             __uint_as_float(y4[t]), acc[i][j], 0, 0, 0);
+                    } else if constexpr (HP == kHpF16) {
+                        typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+                        v8h x8, y8;
+                        __builtin_memcpy(&x8, &x, 16);
+                        __builtin_memcpy(&y8, &y, 16);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x8, y8, acc[i][j], 0, 0, 0);
+                    } else {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(x), as_bf(y), acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+        });
+    };
     auto compute = [&](int stage) {
+        if constexpr (HP >= 0) {
+            compute_hp(stage);
+            return;
+        }
         if constexpr (pf_exact_dma(PF)) {
             if constexpr (SP) compute_exact_sp(stage);
             else compute_exact(stage);

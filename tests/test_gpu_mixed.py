@@ -161,7 +161,7 @@ def test_chain_rejects_bad_stages(gpu):
 
 @pytest.mark.parametrize("tile_rows", [64, 128, 256])
 @pytest.mark.parametrize("ab", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("M,N,K", [(300, 200, 1000), (513, 257, 136), (40, 600, 3600)])
+@pytest.mark.parametrize("M,N,K", [(300, 200, 1000), (513, 257, 136), (40, 600, 3600), (77, 300, 1001)])
 def test_hp_gemm_every_tile(gpu, tile_rows, ab, M, N, K):
     """Each tile of the FP32 / 16-bit GEMM (64 x 64 and 128 x 128 on 256-byte
     LDS rows, 256 x 256 with 8 waves on 128-byte rows) on ragged shapes."""
