@@ -525,12 +525,19 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     static_assert(S::NSTAGE == NS, "stage count");
     constexpr int QA = S::A_BYTES / 1024, QM = S::M_BYTES / 1024, QB = S::B_BYTES / 1024;
     static_assert(S::A_BYTES % 1024 == 0 && S::M_BYTES % 1024 == 0 && S::B_BYTES % 1024 == 0, "1 KiB blocks");
-    static_assert(QM % NW == 0 || QM < NW, "metadata blocks per wave");
-    // full rounds per wave per stage; the first QA % NW (QB % NW) waves take
-    // one more A (B) block
-    constexpr int RA = QA / NW, RB = QB / NW, RM = QM / NW;
-    constexpr int XA = QA % NW, XB = QB % NW;
-    constexpr int PER = RA + RB + RM;                          // DMA instructions per wave per stage (at least)
+    // Loader waves.  With two waves per SIMD (NW = 8), only waves 0-3 (one
+    // per SIMD) issue the loads: a wave waits at each load until the texture
+    // path takes it, and a CU's loads of a stage take that path about 1000
+    // cycles, so if both waves of a SIMD issued loads after the barrier both
+    // would wait and the matrix core would idle; this way the other wave of
+    // each SIMD runs its MFMAs meanwhile.
+    constexpr int ND = (NW == 8 && QA % 4 == 0 && QB % 4 == 0 && (QM % 4 == 0 || QM < 4)) ? 4 : NW;
+    static_assert(QM % ND == 0 || QM < ND, "metadata blocks per wave");
+    // full rounds per loader wave per stage; the first QA % ND (QB % ND)
+    // loader waves take one more A (B) block
+    constexpr int RA = QA / ND, RB = QB / ND, RM = QM / ND;
+    constexpr int XA = QA % ND, XB = QB % ND;
+    constexpr int PER = RA + RB + RM;                          // DMA instructions per loader wave per stage (at least)
     static_assert((NS - 2) * PER < 64, "vmcnt range");
 
     const int tid = threadIdx.x;
@@ -550,8 +557,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     const __amdgpu_buffer_rsrc_t rs_b = uniform_rsrc(p.b + (int64_t)n0 * p.ldb, rec_b);
     const __amdgpu_buffer_rsrc_t rs_m = uniform_rsrc(SP ? p.meta + (int64_t)m0 * p.ldm : p.a, rec_m);
 
-    // Per-lane source of the first block a wave fills; later rounds move
-    // down by NW blocks (a whole number of rows).  Dense rows (128 bytes):
+    // Per-lane source of the first block a loader wave fills; later rounds
+    // move down by ND blocks (a whole number of rows).  Dense rows (128 bytes):
     // block q holds rows 8q .. 8q+7, lane l row 8q + l/8, slot l%8, so the
     // source chunk is (l%8) ^ (l/8) ^ (q&1); round u of an odd number of
     // waves flips the last term, so a second offset serves those rounds.
@@ -570,7 +577,9 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
     const int voff_m = (wave * 64 + lane) * (int)p.ldm;
     const uint32_t lds0 = (uint32_t)(uintptr_t)smem;
 
+    const bool loader = wave < ND;
     auto issue = [&](int kt, int stage) {
+        if (!loader) return;
         const int k0 = kbeg + kt * kBK;
         const uint32_t sb = lds0 + stage * S::STAGE;
         // whole chunks past the end of K read as zero: point them past the range
@@ -583,20 +592,20 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
         constexpr int rows_a_blk = SP ? 16 : 8;   // rows per 1 KiB block
         static_for<0, RA>([&](auto uu) {
             constexpr int u = decltype(uu)::value;
-            dma16(sb + (wave + u * NW) * 1024, ((u * NW) & 1) ? vaf : va, rs_a,
-                  u * NW * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
+            dma16(sb + (wave + u * ND) * 1024, ((u * ND) & 1) ? vaf : va, rs_a,
+                  u * ND * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
         });
         if constexpr (XA > 0) {
             if (wave < XA)
-                dma16(sb + (wave + RA * NW) * 1024, ((RA * NW) & 1) ? vaf : va, rs_a,
-                      RA * NW * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
+                dma16(sb + (wave + RA * ND) * 1024, ((RA * ND) & 1) ? vaf : va, rs_a,
+                      RA * ND * rows_a_blk * (int)p.lda + (SP ? k0 / 2 : k0));
         }
         if constexpr (SP) {
             const int vm = k0 / 8 < Km ? voff_m : rec_m;
             if constexpr (RM > 0) {
                 static_for<0, RM>([&](auto uu) {
                     constexpr int u = decltype(uu)::value;
-                    dma16(sb + S::A_BYTES + (wave + u * NW) * 1024, vm, rs_m, u * NW * 64 * (int)p.ldm + k0 / 8);
+                    dma16(sb + S::A_BYTES + (wave + u * ND) * 1024, vm, rs_m, u * ND * 64 * (int)p.ldm + k0 / 8);
                 });
             } else {
                 if (wave < QM) dma16(sb + S::A_BYTES + wave * 1024, vm, rs_m, k0 / 8);
@@ -604,13 +613,13 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
         }
         static_for<0, RB>([&](auto uu) {
             constexpr int u = decltype(uu)::value;
-            dma16(sb + S::A_BYTES + S::M_BYTES + (wave + u * NW) * 1024, ((u * NW) & 1) ? vbf : vb, rs_b,
-                  u * NW * 8 * (int)p.ldb + k0);
+            dma16(sb + S::A_BYTES + S::M_BYTES + (wave + u * ND) * 1024, ((u * ND) & 1) ? vbf : vb, rs_b,
+                  u * ND * 8 * (int)p.ldb + k0);
         });
         if constexpr (XB > 0) {
             if (wave < XB)
-                dma16(sb + S::A_BYTES + S::M_BYTES + (wave + RB * NW) * 1024, ((RB * NW) & 1) ? vbf : vb, rs_b,
-                      RB * NW * 8 * (int)p.ldb + k0);
+                dma16(sb + S::A_BYTES + S::M_BYTES + (wave + RB * ND) * 1024, ((RB * ND) & 1) ? vbf : vb, rs_b,
+                      RB * ND * 8 * (int)p.ldb + k0);
         }
     };
 
