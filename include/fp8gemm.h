@@ -117,7 +117,10 @@ typedef struct {
  * BF16 and summed on the BF16 MFMA, whose error stays inside the bound
  * 4 K 2^-24 sum |a b| for every K; the FP8 MFMA tiles guarantee that bound
  * only for K >= 3584, so plans the library chooses use exact-sum tiles below
- * that K).  Any out pointer may be NULL.  FP8_ERR_ARG past the last tile. */
+ * that K).  The exact-sum tiles that stage FP8 codes through the LDS-DMA
+ * ring need K to be a multiple of 16 (128 with a 2:4 operand); a plan naming
+ * one for any other K runs on the register-staged exact-sum tile 27.  Any out
+ * pointer may be NULL.  FP8_ERR_ARG past the last tile. */
 fp8_status fp8_tile_info(int tile, int *block_m, int *block_n, int *waves, int *sparse, int *dense,
                          int *exact);
 int fp8_num_tiles(void);
