@@ -286,7 +286,7 @@ def test_exact_tiles_fast_and_byte_loaders(gpu, tile, M, N, K, sparse):
         check_gemm(c, qa_eff, 0, qb, 0, da, db, False, f"exact tile {tile} {M}x{N}x{K} sparse={sparse} split={split}")
 
 
-@pytest.mark.parametrize("M,N,K", [(2048, 2048, 2048), (4096, 1536, 1024), (1024, 1024, 1024)])
+@pytest.mark.parametrize("M,N,K", [(2048, 2048, 2048), (4096, 1536, 1024), (1024, 1024, 1024), (8192, 8192, 2048)])
 @pytest.mark.parametrize("sparse", [False, True])
 def test_exact_default_plan_sampled(gpu, M, N, K, sparse):
     """The library's own plan below K = 3584 at sweep sizes (many tiles of
