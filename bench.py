@@ -384,6 +384,50 @@ def bench_mixed(lib, stream, M=4096, H=2048, n_chains=8, streams=4):
     return res
 
 
+PEAK_BF16_TFLOPS = 2500.0   # dense 16-bit MFMA peak of MI355X (the exact-sum tiles run the BF16 MFMA)
+
+
+def bench_exact(lib, stream, iters=20):
+    """The exact-sum tiles (K below 3584: FP8 decoded exactly to BF16 and
+    summed on the BF16 MFMA): the default plan and each exact tile, dense and
+    2:4 (A side, on the pruned A), against the BF16 roofline."""
+    import torch
+    from paper_2602_10262_amd import synth
+    out = []
+    exact_tiles = [t for t in range(lib.fp8_num_tiles()) if lib.fp8_tile_info(t)["exact"]]
+    for (M, N, K) in ((1024, 1024, 1024), (2048, 2048, 2048), (3072, 3072, 3072), (8192, 8192, 2048)):
+        xa = torch.from_numpy(synth.normal_outliers(7, (M, K))).cuda()
+        xb = torch.from_numpy(synth.normal_outliers(8, (N, K))).cuda()
+        qa, _, da = lib.fp8_quantize(xa, 0, lib.FP8_SCALE_ROW, stream=stream)
+        qb, _, db = lib.fp8_quantize(xb, 0, lib.FP8_SCALE_ROW, stream=stream)
+        del xa, xb
+        values, meta, _ = lib.fp8_sparse24_prune_compress(qa, 0, with_mask=False, stream=stream)
+        pruned = lib.fp8_sparse24_decompress(values, meta, K)
+        c = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+        flops = 2.0 * M * N * K
+        row = {"M": M, "N": N, "K": K,
+               "default_plan": lib.fp8_gemm_plan_resolve(lib.gemm_args(pruned, qb, da, db, c)), "tiles": {}}
+        for _ in range(20):   # clocks up before the first timed plan
+            lib.fp8_gemm(pruned, qb, da, db, c=c, stream=stream)
+        for plan in [None] + [(t, 1) for t in exact_tiles]:
+            key = "default" if plan is None else str(plan[0])
+            dense = lambda: lib.fp8_gemm(pruned, qb, da, db, c=c, plan=plan, stream=stream)
+            sparse = lambda: lib.fp8_sparse24_gemm(values, meta, qb, lib.FP8_SPARSE_A, da, db, c=c, plan=plan,
+                                                   stream=stream)
+            r = {}
+            for name, f in (("dense", dense), ("sparse", sparse)):
+                for _ in range(3):
+                    f()
+                ms = time_events(f, iters, stream)
+                r[name + "_tflops"] = flops / ms / 1e9
+                r[name + "_frac_of_bf16_peak"] = r[name + "_tflops"] / PEAK_BF16_TFLOPS
+            row["tiles"][key] = r
+        out.append(row)
+        del qa, qb, values, meta, pruned, c
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_batching(lib, stream, batch_sizes=(4, 8, 16, 32), seeds=(0, 1, 2)):
     """Should the server batch the requests it admits together into one
     grouped launch?  For batches of B requests drawn from the served workload
@@ -814,6 +858,7 @@ def main():
     ap.add_argument("--ubench-only", action="store_true", help="only the matrix-core and LDS microbenchmarks")
     ap.add_argument("--mixed-only", action="store_true", help="only the mixed-precision GEMMs and chains")
     ap.add_argument("--batching-only", action="store_true", help="only the per-request vs grouped batch study")
+    ap.add_argument("--exact-only", action="store_true", help="only the exact-sum tiles (K below 3584)")
     ap.add_argument("--served-only", action="store_true",
                     help="only the served stream (with --served-sweep: all rates and budgets)")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
@@ -835,8 +880,10 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     M = N = K = args.size
-    if args.ace_only or args.ubench_only or args.mixed_only or args.batching_only or args.served_only:
-        if args.served_only:
+    if args.ace_only or args.ubench_only or args.mixed_only or args.batching_only or args.served_only or args.exact_only:
+        if args.exact_only:
+            res = {"exact": bench_exact(lib, stream)}
+        elif args.served_only:
             if args.served_sweep:
                 res = {"served": bench_served(lib, n_requests=args.requests,
                                               rates=(0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 2.0),
@@ -916,6 +963,7 @@ def main():
     extra["sparse24"] = bench_sparse(lib, qa, da, qb, db, max(5, args.steps // 2), 3, stream)
     extra["ubench"] = bench_ubench(lib, stream)
     extra["encode"] = bench_encode(lib, stream)
+    extra["exact"] = bench_exact(lib, stream)
     log(f"2:4: {extra['sparse24']['sparse_tflops_dense_equiv']:.1f} TFLOP/s dense-equivalent, "
         f"{extra['sparse24']['speedup_vs_dense']:.2f}x vs dense on the pruned matrix")
     del xa, xb, c
