@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # The GEMM tile table is instantiated over several files so that it compiles in
 # parallel; the slowest files come first.
 SOURCES = ["gemm_tiles_b.hip", "gemm_tiles_c.hip", "gemm_tiles_d.hip", "gemm_tiles_e.hip", "gemm_tiles_f.hip",
-           "gemm_tiles_g.hip", "gemm_tiles_h.hip", "gemm_tiles_i.hip", "gemm_tiles_j.hip", "gemm_tiles_a.hip", "gemm_both_a.hip", "gemm_both_b.hip", "grouped_tiles_a.hip", "grouped_tiles_b.hip",
+           "gemm_tiles_g.hip", "gemm_tiles_h.hip", "gemm_tiles_i.hip", "gemm_tiles_j.hip", "gemm_tiles_k.hip", "gemm_tiles_a.hip", "gemm_both_a.hip", "gemm_both_b.hip", "grouped_tiles_a.hip", "grouped_tiles_b.hip",
            "grouped_tiles_c.hip", "grouped_tiles_d.hip", "grouped.hip", "gemm.hip", "quantize.hip", "quantize_prune.hip", "sparse24.hip", "validate.hip",
            "noalloc.hip", "ubench.hip", "gemm_hp.hip", "api.cpp", "tune.cpp", "server.cpp", "chain.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

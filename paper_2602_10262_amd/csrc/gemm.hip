@@ -7,7 +7,7 @@
 namespace fp8k {
 
 #define FP8_DESC(i, bm, bn, wm, wn, occ, pf)                                                     \
-    {bm, bn, wm * wn, (tile_sparse_ok(bm) || pf == kExactPF) ? 1 : 0, pf_exact(pf) ? 1 : 0, \
+    {bm, bn, wm * wn, ((tile_sparse_ok(bm) || pf == kExactPF) && !pf_mfma32(pf)) ? 1 : 0, pf_exact(pf) ? 1 : 0, \
      tile_dense_fits(bm, bn, pf) ? 1 : 0},
 static const TileDesc kTiles[] = {FP8_TILE_LIST(FP8_DESC)};
 #undef FP8_DESC

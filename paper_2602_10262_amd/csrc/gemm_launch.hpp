@@ -47,7 +47,7 @@ hipError_t launch_one(int fa, int fb, bool sp, const GemmParams &p, hipStream_t 
     dim3 grid((unsigned)nb, 1, (unsigned)p.splits), block(WM * WN * 64);
 #define FP8_GO(FA, FB, SP) gemm_kernel<BM, BN, WM, WN, OCC, PF, FA, FB, SP, KFAST><<<grid, block, 0, st>>>(p)
     constexpr bool DENSE = tile_dense_fits(BM, BN, PF);
-    constexpr bool SPARSE = tile_sparse_ok(BM) || PF == kExactPF;
+    constexpr bool SPARSE = (tile_sparse_ok(BM) || PF == kExactPF) && !pf_mfma32(PF);
     // (plan resolution rejects a dense or 2:4 request for a tile without that kernel)
     if (sp) {
         if constexpr (SPARSE) {

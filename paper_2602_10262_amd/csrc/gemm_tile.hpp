@@ -38,6 +38,9 @@ constexpr int kExactPF = 40;
 constexpr bool pf_exact_dma(int pf) { return pf >= kExactPF + 2 && pf <= kExactPF + 4; }
 constexpr bool pf_exact(int pf) { return pf == kExactPF || pf_exact_dma(pf); }
 constexpr int kExactAnyKTile = 27;
+// Pipelines 56 .. 58: the FP8 LDS-DMA ring with PF - 54 stages on the
+// 32 x 32 x 64 MFMA instead of the 16 x 16 x 128 one (dense operands).
+constexpr bool pf_mfma32(int pf) { return pf >= 56 && pf <= 58; }
 // Operand types of the higher-precision GEMMs (the DMA ring's HP parameter;
 // -1 there means FP8 codes).
 constexpr int kHpF32 = 0, kHpF16 = 1, kHpBF16 = 2;
@@ -93,7 +96,8 @@ __device__ __forceinline__ void static_for(F &&f)
     X(27, 128, 128, 2, 4, 1, 40)   \
     X(28, 128, 128, 2, 4, 1, 44)   \
     X(29, 256, 128, 4, 2, 1, 43)   \
-    X(30, 256, 256, 2, 4, 1, 42)
+    X(30, 256, 256, 2, 4, 1, 42)   \
+    X(31, 256, 256, 2, 4, 1, 56)
 
 
 // Whether a tile of BM rows has a 2:4 kernel: its compressed rows fill whole
@@ -108,7 +112,10 @@ constexpr int kMaxLdsBytes = 160 * 1024;   // LDS of one CU (gfx950)
 // the exact-sum DMA loops.
 constexpr int pf_stages(int pf)
 {
-    return pf == 3 ? 3 : (pf == kExactPF ? 2 : (pf_exact_dma(pf) ? pf - kExactPF : (pf >= 6 ? pf - 4 : 2)));
+    return pf == 3 ? 3
+                   : (pf == kExactPF ? 2
+                                     : (pf_exact_dma(pf) ? pf - kExactPF
+                                                         : (pf_mfma32(pf) ? pf - 54 : (pf >= 6 ? pf - 4 : 2))));
 }
 
 // LDS of one tile: NSTAGE stages.
@@ -751,7 +758,54 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
             }
         });
     };
+    // 32 x 32 x 64 instructions (pf_mfma32): lane l supplies row l % 32 and
+    // codes 32 g .. 32 g + 31 (g = l / 32) of each 64-code half hk of the
+    // step, i.e. chunks 4 hk + 2 g and 4 hk + 2 g + 1; rows 32 apart share
+    // their swizzle phase.  Each 32 x 32 block accumulates in 16 registers.
+    constexpr int TM2 = TM / 2 > 0 ? TM / 2 : 1, TN2 = TN / 2 > 0 ? TN / 2 : 1;
+    v16f acc32[TM2][TN2];
+    if constexpr (pf_mfma32(PF)) {
+        static_assert(TM % 2 == 0 && TN % 2 == 0 && !SP && !SWAP, "32 x 32 blocks");
+#pragma unroll
+        for (int i = 0; i < TM2; ++i)
+#pragma unroll
+            for (int j = 0; j < TN2; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc32[i][j][e] = 0.f;
+    }
+    const int r32 = lane & 31, g32 = lane >> 5;
+    const int ra32 = wm * WTM + r32, rb32 = wn * WTN + r32;
+    auto compute_32 = [&](int stage) {
+        const uint8_t *base = smem + stage * S::STAGE;
+        static_for<0, 2>([&](auto hh) {
+            constexpr int hk = decltype(hh)::value;
+            const int c0 = 4 * hk + 2 * g32;
+            const int ob = S::A_BYTES + swz(rb32, c0), ob1 = S::A_BYTES + swz(rb32, c0 + 1);
+            const int oa = swz(ra32, c0), oa1 = swz(ra32, c0 + 1);
+            v8i bf[TN2];
+#pragma unroll
+            for (int j = 0; j < TN2; ++j) {
+                const uint4 lo = *reinterpret_cast<const uint4 *>(base + ob + j * 4096);
+                const uint4 hi = *reinterpret_cast<const uint4 *>(base + ob1 + j * 4096);
+                bf[j] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+#pragma unroll
+            for (int i = 0; i < TM2; ++i) {
+                const uint4 lo = *reinterpret_cast<const uint4 *>(base + oa + i * 4096);
+                const uint4 hi = *reinterpret_cast<const uint4 *>(base + oa1 + i * 4096);
+                const v8i af = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+#pragma unroll
+                for (int j = 0; j < TN2; ++j)
+                    acc32[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, bf[j], acc32[i][j], FA, FB, 0, 0,
+                                                                                 0, 0);
+            }
+        });
+    };
     auto compute = [&](int stage) {
+        if constexpr (pf_mfma32(PF)) {
+            compute_32(stage);
+            return;
+        }
         if constexpr (HP >= 0) {
             compute_hp(stage);
             return;
@@ -807,6 +861,34 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
         wait_vm<0>();
     }
 
+    if constexpr (pf_mfma32(PF)) {
+        // Each 32 x 32 block to the four 16 x 16 blocks the epilogue takes.
+        // 32 x 32 layout: element (i, j) in lane j + 32 ((i / 4) % 2),
+        // register (i % 4) + 4 (i / 8).  16 x 16 layout (unswapped): lane L
+        // holds rows 4 (L / 16) .. + 3 of column L % 16.  So value q of lane L
+        // in 16 x 16 block (a, b) comes from lane 16 b + L % 16 + 32 ((L / 16)
+        // % 2), register 8 a + 4 (L / 32) + q.
+        static_for<0, TM2>([&](auto ii) {
+            constexpr int i2 = decltype(ii)::value;
+            static_for<0, TN2>([&](auto jj) {
+                constexpr int j2 = decltype(jj)::value;
+                const v16f x = acc32[i2][j2];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int src = (16 * b + (lane & 15) + 32 * ((lane >> 4) & 1)) * 4;
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int y0 = __builtin_amdgcn_ds_bpermute(src, __float_as_int(x[8 * a + q]));
+                            const int y1 = __builtin_amdgcn_ds_bpermute(src, __float_as_int(x[8 * a + 4 + q]));
+                            acc[2 * i2 + a][2 * j2 + b][q] = __int_as_float(lane < 32 ? y0 : y1);
+                        }
+                    }
+                }
+            });
+        });
+    }
     static_assert(!(SP && SWAP), "the compressed operand must stay in the MFMA A slot");
     write_tile<BM, BN, WM, WN, SWAP, S::TOTAL>(p, acc, m0, n0, wave, lane, split, smem);
 }
@@ -1125,6 +1207,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams &p, int tm, int tn, i
 {
     if constexpr (PF == kExactPF) {
         gemm_tile_exact<BM, BN, WM, WN, FA, FB, SP, SPB, KFAST>(p, tm, tn, split, smem);
+        return;
+    } else if constexpr (pf_mfma32(PF)) {
+        static_assert(KFAST && !SP && !SPB, "32 x 32 MFMA ring: dense operands, whole 16-byte chunks");
+        gemm_tile_dma<BM, BN, WM, WN, FA, FB, false, PF - 54, PF, false>(p, tm, tn, split, smem);
         return;
     } else if constexpr (pf_exact_dma(PF)) {
         static_assert(KFAST && !SPB, "exact sums on the DMA ring: whole 16-byte chunks, dense j operand");

@@ -42,7 +42,7 @@ def test_dense_ragged_shapes(gpu, M, N, K, fa, bf16):
     check_gemm(c, qa, fa, qb, 0, da, db, bf16, f"{M}x{N}x{K}")
 
 
-NUM_TILES = 31   # tile configurations the library exports (fp8_num_tiles)
+NUM_TILES = 32   # tile configurations the library exports (fp8_num_tiles)
 # FP8 decoded to BF16 and summed on the BF16 MFMA: 25-27 through registers
 # (any K), 28-30 on the LDS-DMA ring (K % 16 == 0, or % 128 with a 2:4
 # operand; any other K runs on tile 27); dense and 2:4 alike
