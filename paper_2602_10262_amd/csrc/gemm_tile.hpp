@@ -274,6 +274,18 @@ __device__ __forceinline__ void store4(const GemmParams &p, int i, int j, int sp
     }
 }
 
+// Orders a wave's LDS accesses across lanes without a workgroup barrier:
+// the instructions of one wave reach the LDS in program order, so only the
+// compiler has to be kept from moving accesses across this point (the
+// fences at wavefront scope) and the wave's own LDS operations must have
+// completed.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The staged store of write_tile for one output orientation: TR = the
 // result is stored transposed (output rows are j).  Pass t covers the
 // sixteen output rows of MFMA block t along the output-row index.  The
@@ -352,7 +364,7 @@ __device__ __forceinline__ void write_tile_staged(const GemmParams &p, const v4f
                 }
             });
         }
-        __syncthreads();
+        wave_sync();
         // store 16-byte chunks of whole output rows, times the column descale
         for (int r = rsub; r < 16; r += rstep) {
             const int orow = orow0 + t * 16 + r;
@@ -381,7 +393,7 @@ __device__ __forceinline__ void write_tile_staged(const GemmParams &p, const v4f
                     for (int e = 0; e < 4 && ocol + e < cols_out; ++e) reinterpret_cast<float *>(dst)[e] = v[e];
             }
         }
-        __syncthreads();
+        wave_sync();   // the next pass rewrites the region these reads use
     });
 }
 
@@ -389,7 +401,9 @@ __device__ __forceinline__ void write_tile_staged(const GemmParams &p, const v4f
 // The output is staged through the wave's own region of LDS, sixteen output
 // rows at a time, so that global stores are 16-byte chunks of whole rows
 // (a wave writes 64 to 512 contiguous bytes of each row) instead of the
-// 8-byte pieces of sixteen rows that one MFMA result holds.  The value is
+// 8-byte pieces of sixteen rows that one MFMA result holds.  Only the first
+// pass waits for the whole workgroup (the main loop's LDS is shared); the
+// passes themselves touch only the wave's own region.  The value is
 // (acc * d_i) * d_j (transposed output: (acc * d_j) * d_i) in FP32: the
 // staged value carries the output row's descale, the column's is applied
 // when the row chunk is stored, as FP32, BF16 or FP16 (both RNE).  Split-K partial
