@@ -501,6 +501,23 @@ __device__ __forceinline__ void decode16(const uint4 &q, uint4 &lo, uint4 &hi)
                     fp8x2_to_bf16x2<FMT, false>(q.w), fp8x2_to_bf16x2<FMT, true>(q.w));
 }
 
+// 16 kept codes of 32 dense positions (two per group of four, ascending) and
+// their eight index nibbles -> the 32 dense codes (zeros elsewhere)
+__device__ __forceinline__ void expand24(const uint4 &v, uint32_t meta, uint4 &d0, uint4 &d1)
+{
+    uint32_t kept[4] = {v.x, v.y, v.z, v.w}, dense[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+        const uint32_t nib = (meta >> (4 * g)) & 15u;
+        const uint32_t i0 = nib & 3u, i1 = nib >> 2;
+        const uint32_t c0 = (kept[g / 2] >> (16 * (g & 1))) & 0xFFu, c1 = (kept[g / 2] >> (16 * (g & 1) + 8)) & 0xFFu;
+        // group g occupies dense word g: byte i0 <- c0, byte i1 <- c1 (i0 < i1)
+        dense[g] = (c0 << (8 * i0)) | (c1 << (8 * i1));
+    }
+    d0 = make_uint4(dense[0], dense[1], dense[2], dense[3]);
+    d1 = make_uint4(dense[4], dense[5], dense[6], dense[7]);
+}
+
 // 8 kept codes of 16 dense positions (two per group of four, ascending) and
 // their four index nibbles -> the 16 dense codes (zeros elsewhere)
 __device__ __forceinline__ uint4 expand24_half(uint2 v, uint32_t nibs)
@@ -702,40 +719,42 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
             }
         });
     };
-    // The same with a compressed A: dense chunk x = 4 h + lg of a row is
-    // kept codes 8 x .. 8 x + 7 (half x % 2 of compressed chunk x / 2) and
-    // index nibbles 4 x .. 4 x + 3 (16 bits at byte 2 x of the row's
-    // metadata), expanded to 16 dense codes before the decode.
+    // The same with a compressed A.  Here lane group g feeds dense chunk
+    // 2 g + h in pass h (A and B alike): one 128-bit read of compressed
+    // chunk g (16 kept codes) and its 32-bit index word cover both passes,
+    // the same reads the 2:4 FP8 instruction makes; the 32 dense codes they
+    // expand to are decoded once per step.
     auto compute_exact_sp = [&](int stage) {
         const uint8_t *base = smem + stage * S::STAGE;
+        v8bf blo[2][TN], bhi[2][TN];
         static_for<0, 2>([&](auto hh) {
             constexpr int h = decltype(hh)::value;
-            const int x = 4 * h + lg;
-            const int ob = S::A_BYTES + S::M_BYTES + swz_b2(rb0, x);
-            const int oa = swz_sp(ra0, x >> 1) + 8 * (x & 1), om = S::A_BYTES + ra0 * 16 + 2 * x;
-            v8bf blo[TN], bhi[TN];
+            const int ob = S::A_BYTES + S::M_BYTES + swz_b2(rb0, 2 * lg + h);
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 uint4 lo, hi;
                 decode16<FB>(*reinterpret_cast<const uint4 *>(base + ob + j * 2048), lo, hi);
-                blo[j] = as_bf(lo);
-                bhi[j] = as_bf(hi);
-            }
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const uint2 kept = *reinterpret_cast<const uint2 *>(base + oa + i * 1024);
-                const uint32_t nibs = *reinterpret_cast<const uint16_t *>(base + om + i * 256);
-                uint4 lo, hi;
-                decode16<FA>(expand24_half(kept, nibs), lo, hi);
-                const v8bf alo = as_bf(lo), ahi = as_bf(hi);
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, blo[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi[j], acc[i][j], 0, 0, 0);
+                blo[h][j] = as_bf(lo);
+                bhi[h][j] = as_bf(hi);
             }
         });
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const uint4 kept = *reinterpret_cast<const uint4 *>(base + oa0 + i * 1024);
+            const uint32_t meta = *reinterpret_cast<const uint32_t *>(base + oa1 + i * 256);
+            uint4 d0, d1, l0, h0, l1, h1;
+            expand24(kept, meta, d0, d1);
+            decode16<FA>(d0, l0, h0);
+            decode16<FA>(d1, l1, h1);
+            const v8bf a[4] = {as_bf(l0), as_bf(h0), as_bf(l1), as_bf(h1)};
+            // (the four MFMAs into one accumulator are TN instructions apart)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        a[t], (t & 1) ? bhi[t >> 1][j] : blo[t >> 1][j], acc[i][j], 0, 0, 0);
+        }
     };
     auto compute_hp = [&](int stage) {
         static_assert(HP < 0 || (!SP && !pf_exact_dma(PF)), "higher-precision operands: dense FP8-layout ring");
@@ -928,22 +947,6 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams &p, int tm, int t
 // ring, pf_exact_dma, which keeps FP8 codes in LDS and decodes after the
 // fragment reads: half the LDS bytes per step.)
 
-// 16 kept codes of 32 dense positions (two per group of four, ascending) and
-// their eight index nibbles -> the 32 dense codes (zeros elsewhere)
-__device__ __forceinline__ void expand24(const uint4 &v, uint32_t meta, uint4 &d0, uint4 &d1)
-{
-    uint32_t kept[4] = {v.x, v.y, v.z, v.w}, dense[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int g = 0; g < 8; ++g) {
-        const uint32_t nib = (meta >> (4 * g)) & 15u;
-        const uint32_t i0 = nib & 3u, i1 = nib >> 2;
-        const uint32_t c0 = (kept[g / 2] >> (16 * (g & 1))) & 0xFFu, c1 = (kept[g / 2] >> (16 * (g & 1) + 8)) & 0xFFu;
-        // group g occupies dense word g: byte i0 <- c0, byte i1 <- c1 (i0 < i1)
-        dense[g] = (c0 << (8 * i0)) | (c1 << (8 * i1));
-    }
-    d0 = make_uint4(dense[0], dense[1], dense[2], dense[3]);
-    d1 = make_uint4(dense[4], dense[5], dense[6], dense[7]);
-}
 
 // Codes [k, k + 16) of a row of `len` codes, zero past the end (byte-exact
 // when the chunk is partial or unaligned).
