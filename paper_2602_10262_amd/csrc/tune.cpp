@@ -123,9 +123,14 @@ void tune_cache_store(const GemmKey &k, const fp8_plan &plan, double us)
     g_cache[make_key(k)] = Entry{plan, us};
 }
 
-// Median time in microseconds of `iters` calls of fn on st (after two warm-up calls).
+// Median time in microseconds of `iters` calls of fn on st (after two warm-up
+// calls).  With `flush`, flush_bytes of it are rewritten before every timed
+// call, outside the timed interval, so that operands small enough to stay in
+// the 256 MB memory-side cache are read from HBM again, as a stream of
+// distinct problems would read them.
 template <typename F>
-static fp8_status time_median(F &&fn, int iters, hipStream_t st, double *us)
+static fp8_status time_median(F &&fn, int iters, hipStream_t st, double *us, void *flush = nullptr,
+                              size_t flush_bytes = 0)
 {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return set_error(FP8_ERR_HIP, "event creation failed");
@@ -137,6 +142,10 @@ static fp8_status time_median(F &&fn, int iters, hipStream_t st, double *us)
     for (int w = 0; w < 2 && s == FP8_OK; ++w) s = fn();
     std::vector<float> times;
     for (int i = 0; i < iters && s == FP8_OK; ++i) {
+        if (flush && hipMemsetAsync(flush, i & 0xff, flush_bytes, st) != hipSuccess) {
+            s = set_error(FP8_ERR_HIP, "cache flush before a timed call failed");
+            break;
+        }
         (void)hipEventRecord(e0, st);
         s = fn();
         (void)hipEventRecord(e1, st);
@@ -193,18 +202,29 @@ static fp8_status tune_prepared(const Prepared &pr, int iters, hipStream_t st, f
         hipError_t e = hipMalloc(&ws, ws_max);
         if (e != hipSuccess) return hip_error(e, "tuning workspace");
     }
+    // operands that fit in the memory-side cache are flushed from it before
+    // every timed call (twice its size is rewritten)
+    const size_t operand_bytes = (size_t)pr.key.mk * pr.key.kk + (size_t)pr.key.nk * pr.key.kk;
+    const size_t flush_bytes = operand_bytes < ((size_t)512 << 20) ? ((size_t)512 << 20) : 0;
+    void *flush = nullptr;
+    if (flush_bytes && hipMalloc(&flush, flush_bytes) != hipSuccess) {
+        flush = nullptr;             // tune without it
+        (void)hipGetLastError();     // and do not leave the failure for a later launch check
+    }
     double best_t = 1e30;
     fp8_plan best_p = cands[0];
     fp8_status status = FP8_OK;
     for (auto &c : cands) {
         double us = 0;
-        status = time_median([&]() { return run_prepared(pr, c, ws, ws_max, st); }, iters, st, &us);
+        status = time_median([&]() { return run_prepared(pr, c, ws, ws_max, st); }, iters, st, &us, flush,
+                             flush ? flush_bytes : 0);
         if (status != FP8_OK) break;
         if (us < best_t) {
             best_t = us;
             best_p = c;
         }
     }
+    if (flush) (void)hipFree(flush);
     if (ws) (void)hipFree(ws);
     if (status != FP8_OK) return status;
     tune_cache_store(pr.key, best_p, best_t);
