@@ -1,26 +1,29 @@
 // The FP8 GEMM macro-tile shared by the plain, split-K and grouped kernels.
 //
 // One workgroup computes a BM x BN block of C over a K range, in steps of 128
-// codes of K:
-//   - stage loads: 128-bit global loads of step k+2 are issued into one of
-//     two register sets before the MFMAs of step k, and the other set (step
-//     k+1, loaded during step k-1) is written to the other half of a
-//     double-buffered LDS area after them: two steps of compute cover the
-//     global latency and one barrier per step suffices;
-//   - LDS layout: dense operands keep one 128-byte row per tile row, the
-//     sixteen-byte chunks of row r permuted by an XOR with the row number
-//     so that the sixteen rows a fragment read touches spread over all banks;
-//     compressed operands keep 64 value bytes and 16 metadata bytes per row;
-//   - each wave owns a (BM / WM) x (BN / WN) sub-block made of 16 x 16
-//     accumulators; per step it reads its A and B fragments from LDS and
-//     issues v_mfma_f32_16x16x128_f8f6f4 (dense: lane l supplies row l % 16,
-//     codes 32 (l / 16) .. 32 (l / 16) + 31 of the step, for both operands)
-//     or v_smfmac_f32_16x16x128_* (2:4: lane l supplies the 16 survivors of
-//     those 32 positions and their eight index nibbles as one 32-bit word,
-//     while its B lane holds codes 16 (l / 16) + 0..15 and 64 + 16 (l / 16)
-//     + 0..15, the layout the sparse instruction pairs with);
-//   - epilogue: descales applied in FP32, C stored as FP32 or BF16 (RNE), or
-//     raw FP32 partial sums to the split-K workspace.
+// codes of K.  The pipelines (PF in the tile table, see gemm_tile):
+//   - register-staged (PF 1-3): 128-bit global loads of a later step go to
+//     registers before the MFMAs of the current one and are written to the
+//     other half of a double-buffered LDS area after them;
+//   - LDS-DMA ring (PF >= 6): buffer loads straight into LDS, NS stages, one
+//     loader wave per SIMD when a workgroup has two per SIMD;
+//   - exact sums (PF 40 through registers, 42-44 on the DMA ring): FP8 codes
+//     decoded exactly to BF16 and summed on the BF16 MFMA, for K below 3584;
+//   - 32 x 32 x 64 MFMAs on the DMA ring (PF 56);
+//   - FP32 / FP16 / BF16 operands on the DMA ring (the HP parameter).
+// LDS layout: dense operands keep one 128-byte row per tile row, the
+// sixteen-byte chunks of row r permuted by an XOR with the row number so that
+// the rows a fragment read touches spread over all banks; compressed operands
+// keep 64 value bytes and 16 metadata bytes per row.  Each wave owns a
+// (BM / WM) x (BN / WN) sub-block made of 16 x 16 accumulators; per step it
+// reads its A and B fragments from LDS and issues v_mfma_f32_16x16x128_f8f6f4
+// (dense: lane l supplies row l % 16, codes 32 (l / 16) .. 32 (l / 16) + 31 of
+// the step, for both operands) or v_smfmac_f32_16x16x128_* (2:4: lane l
+// supplies the 16 survivors of those 32 positions and their eight index
+// nibbles as one 32-bit word, while its B lane holds codes 16 (l / 16) + 0..15
+// and 64 + 16 (l / 16) + 0..15, the layout the sparse instruction pairs with).
+// Epilogue: descales applied in FP32, C stored as FP32, BF16 or FP16 (RNE), or
+// raw FP32 partial sums to the split-K workspace.
 #pragma once
 #include <type_traits>
 #include "common.hpp"
