@@ -209,10 +209,13 @@ def test_full_size_sampled(gpu, M, N, K, fa):
     check_gemm_sampled(c, qa, fa, qb, 0, da, db, True, what=f"{M}x{N}x{K}")
 
 
-def test_full_size_sparse_sampled(gpu):
+@pytest.mark.parametrize("S", [8192, 16384])
+def test_full_size_sparse_sampled(gpu, S):
+    """2:4 (A pruned) at the sweep's large squares on the default plan."""
     import torch
     from paper_2602_10262_amd import synth
-    M = N = K = 8192
+    M = N = K = S
+    log(f"full size sparse {S}^3")
     xa = synth.normal_outliers(31, (M, K))
     xb = synth.normal_outliers(32, (N, K))
     qa_d, _, da_d = gpu.fp8_quantize(dev(xa), 0, gpu.FP8_SCALE_ROW)
@@ -223,7 +226,7 @@ def test_full_size_sparse_sampled(gpu):
     qa, _, da = orc.quantize(xa, 0, True)
     qb, _, db = orc.quantize(xb, 0, True)
     _, _, _, pa = orc.prune24(qa, 0)
-    check_gemm_sampled(c, pa, 0, qb, 0, da, db, True, what="sparse 8192^3")
+    check_gemm_sampled(c, pa, 0, qb, 0, da, db, True, what=f"sparse {S}^3")
 
 
 # ------------------------------------------- MFMA in-instruction precision ---
